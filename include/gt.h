@@ -1,0 +1,138 @@
+/*
+ * gt.h — stable CSR -> CSC graph transposition on one AMD MI355X (gfx950).
+ *
+ * Operation (Section II-A, Algorithm 1 of "On Optimizing Locality of Graph
+ * Transposition on Modern Architectures"): given a directed graph in CSR form
+ * (offsets[n+1], edges[m] holding destinations, optional 32-bit weight per
+ * edge), produce its CSC form (offsets[n+1], edges[m] holding sources,
+ * weights moved with their edges).  This library fixes the order inside each
+ * CSC list, which the paper leaves open (Section II-B, optional sort): the
+ * slots offsets[v] .. offsets[v+1]-1 hold the in-edges of v in increasing
+ * CSR edge position, i.e. ascending source, and multi-edges from one source
+ * in CSR order.  The result is therefore unique and deterministic.
+ *
+ * Types and layout (all arrays are device memory, owned by the caller):
+ *   offsets  int64[n+1]   offsets[0] = 0, nondecreasing, offsets[n] = m
+ *   indices  int32[m]     0 <= indices[e] < n;  n <= 2^31 - 1
+ *   payload  uint32[m]    optional; 32-bit words copied bit-exactly (a float
+ *                         payload is passed as its bit pattern)
+ * Output arrays (caller-allocated, must not alias the input):
+ *   offsets int64[n+1], indices int32[m], payload uint32[m] (NULL iff the
+ *   input payload is NULL).
+ *
+ * Workspace: the library never allocates or frees device memory.  The caller
+ * asks gt_workspace_size() for a byte count and passes a device buffer of at
+ * least that size; its contents need no initialisation and are clobbered.
+ *
+ * Streams: gt_transpose / gt_transpose_batched enqueue kernels on `stream`
+ * and return without synchronising, so they may be captured into a HIP graph.
+ * gt_plan synchronises `stream` once when its policy samples the graph.
+ * A plan and a workspace must not be used by two streams at the same time.
+ *
+ * Errors: argument and size problems are reported synchronously by the
+ * return code; nothing throws across this interface.  Conditions found on the
+ * device (an invalid graph when validation is on) are written to a status
+ * word in the workspace and read with gt_device_status() after the stream
+ * has been synchronised.
+ */
+#ifndef GT_H
+#define GT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GT_OK = 0,
+  GT_ERR_INVALID_ARGUMENT = 1,   /* NULL pointer, negative size, n > 2^31-1, payload mismatch */
+  GT_ERR_INVALID_GRAPH = 2,      /* device-detected: bad offsets or an index outside [0, n) */
+  GT_ERR_WORKSPACE_TOO_SMALL = 3,
+  GT_ERR_UNSUPPORTED = 4,        /* e.g. a parameter outside the compiled kernel variants */
+  GT_ERR_HIP = 5                 /* a HIP runtime call failed */
+} gt_status;
+
+/* A CSR graph (input).  Device pointers; payload may be NULL. */
+typedef struct {
+  int64_t n, m;
+  const int64_t *offsets;
+  const int32_t *indices;
+  const uint32_t *payload;
+} gt_csr_t;
+
+/* A CSC graph (output).  Device pointers; payload NULL iff the input's is. */
+typedef struct {
+  int64_t *offsets;
+  int32_t *indices;
+  uint32_t *payload;
+} gt_csc_t;
+
+/* Policies for choosing the kernel parameters of a plan. */
+enum {
+  GT_POLICY_HEURISTIC = 0,  /* sizes and sampled degree features (default) */
+  GT_POLICY_FIXED = 1,      /* use fine_bits / digit_bits / variant as given */
+  GT_POLICY_MLP = 2,        /* learned choice from sampled features (falls back to HEURISTIC) */
+  GT_POLICY_TABLE = 3       /* autotuned table lookup by graph size class */
+};
+
+/* Options; pass NULL for defaults.  Fields set to 0 take their default. */
+typedef struct {
+  int32_t policy;        /* GT_POLICY_* */
+  int32_t fine_bits;     /* log2 of the vertex range sorted in LDS by the last kernel (4..9) */
+  int32_t digit_bits;    /* maximum digit width of one stable partition pass (4..10) */
+  int32_t variant;       /* tile variant of the partition kernels (0 = auto, 1..N) */
+  int32_t validate;      /* 1: check offsets/indices on the device (status word) */
+  uint64_t seed;         /* seed of the degree-sampling pass */
+  const char *model_path;/* weights of the learned policy (GT_POLICY_MLP) */
+} gt_options_t;
+
+typedef struct gt_plan_st *gt_plan_t;
+
+/* Bytes of workspace needed to transpose `count` graphs (any policy). */
+gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out);
+
+/* Build a plan for `count` graphs (count == 1 for gt_transpose).  When the
+ * policy needs sampled features the sampling kernels run on `stream` using
+ * `workspace`, and the stream is synchronised once. */
+gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
+                  size_t workspace_bytes, void *stream, gt_plan_t *plan_out);
+
+/* Transpose one graph (the plan was built with count == 1 for a graph of the
+ * same n, m and payload presence).  Asynchronous on `stream`. */
+gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Transpose `count` graphs in one batched launch sequence (plan built for the
+ * same count and sizes).  Asynchronous on `stream`. */
+gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* After the stream has been synchronised: GT_OK, or GT_ERR_INVALID_GRAPH if
+ * validation found a bad input.  Reads 4 bytes of the workspace. */
+gt_status gt_device_status(const void *workspace);
+
+/* Parameters a plan selected for graph `i` (for reporting and tests). */
+gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits,
+                         int32_t *passes, int32_t *variant);
+
+gt_status gt_plan_destroy(gt_plan_t plan);
+
+/* Per-kernel timing for measurement.  While enabled, gt_transpose records a
+ * HIP event pair around every kernel launch on the launch stream (the
+ * kernels themselves are unchanged).  gt_profile_read waits for the recorded
+ * events, returns per kernel name the summed milliseconds and the number of
+ * launches since profiling was enabled or last read (at most `max_kernels`
+ * names of up to 31 characters), and clears the record. */
+gt_status gt_profile(gt_plan_t plan, int32_t enable);
+gt_status gt_profile_read(gt_plan_t plan, int32_t max_kernels, char (*names)[32], double *total_ms,
+                          int32_t *launches, int32_t *count_out);
+
+const char *gt_status_string(gt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GT_H */

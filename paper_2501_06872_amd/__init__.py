@@ -1,0 +1,209 @@
+"""Python binding of libgt.so: stable CSR -> CSC graph transposition on MI355X.
+
+Argument marshalling only.  Every step of the transposition runs in the HIP
+kernels of ``libgt.so``; PyTorch provides device memory and the stream.  If
+the library has not been built, importing works but every call raises.
+
+    T, S, Q = transpose(offsets, indices, payload=None)
+
+``offsets`` int64[n+1], ``indices`` int32[m], ``payload`` a 32-bit tensor
+(int32/uint32/float32, moved as bit patterns) or None, all on one GPU.
+Returns the CSC offsets (int64[n+1]), sources (int32[m]) and payload
+(same dtype as given, or None).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgt.so")
+
+GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP = \
+    range(6)
+POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP, POLICY_TABLE = range(4)
+
+# Every entry point declared in include/gt.h.
+EXPORTS = ("gt_workspace_size", "gt_plan", "gt_transpose", "gt_transpose_batched", "gt_device_status",
+           "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_status_string")
+
+
+class GTError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("indices", ctypes.c_void_p), ("payload", ctypes.c_void_p)]
+
+
+class CSC(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("indices", ctypes.c_void_p), ("payload", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("fine_bits", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("validate", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("model_path", ctypes.c_char_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgt.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2501_06872_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.gt_workspace_size.argtypes = [P(CSR), i32, P(sz)]
+        L.gt_plan.argtypes = [P(CSR), i32, P(Options), vp, sz, vp, P(vp)]
+        L.gt_transpose.argtypes = [vp, P(CSR), P(CSC), vp, sz, vp]
+        L.gt_transpose_batched.argtypes = [vp, i32, P(CSR), P(CSC), vp, sz, vp]
+        L.gt_device_status.argtypes = [vp]
+        L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
+        L.gt_plan_destroy.argtypes = [vp]
+        L.gt_profile.argtypes = [vp, i32]
+        L.gt_profile_read.argtypes = [vp, i32, vp, vp, vp, P(i32)]
+        L.gt_status_string.argtypes = [ctypes.c_int]
+        L.gt_status_string.restype = ctypes.c_char_p
+        for f in EXPORTS[:-1]:
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    return lib().gt_status_string(int(s)).decode()
+
+
+def _check(rc, what):
+    if rc != GT_OK:
+        raise GTError(rc, what)
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _csr(offsets, indices, payload):
+    n = offsets.numel() - 1
+    m = indices.numel()
+    return CSR(n, m, offsets.data_ptr(), indices.data_ptr() if m else None,
+               payload.data_ptr() if payload is not None and m else (1 if payload is not None else None))
+
+
+def _check_inputs(offsets, indices, payload):
+    if not (offsets.is_cuda and indices.is_cuda):
+        raise ValueError("offsets and indices must be GPU tensors")
+    if offsets.dtype != torch.int64 or indices.dtype != torch.int32:
+        raise ValueError("offsets must be int64 and indices int32")
+    if not (offsets.is_contiguous() and indices.is_contiguous()):
+        raise ValueError("inputs must be contiguous")
+    if payload is not None:
+        if payload.element_size() != 4 or payload.numel() != indices.numel() or not payload.is_contiguous():
+            raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
+
+
+def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
+                 model_path=None):
+    return Options(policy, fine_bits, digit_bits, variant, int(bool(validate)), seed,
+                   model_path.encode() if model_path else None)
+
+
+class Plan:
+    """A plan plus its workspace for graphs of fixed sizes.
+
+    ``Plan([(offsets, indices, payload), ...], options)``; call ``run`` (one
+    graph) or ``run_batched`` (all graphs) with tensors of the same sizes.
+    """
+
+    def __init__(self, graphs, options=None, device=None):
+        L = lib()
+        self.device = device if device is not None else graphs[0][0].device
+        self.count = len(graphs)
+        for g in graphs:
+            _check_inputs(*g)
+        arr = (CSR * self.count)(*[_csr(*g) for g in graphs])
+        self._shapes = [(g[0].numel() - 1, g[1].numel(), g[2] is not None) for g in graphs]
+        ws = ctypes.c_size_t(0)
+        _check(L.gt_workspace_size(arr, self.count, ctypes.byref(ws)), "gt_workspace_size")
+        self.workspace = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        opts = options if options is not None else make_options()
+        _check(L.gt_plan(arr, self.count, ctypes.byref(opts), self.workspace.data_ptr(), self.workspace.numel(),
+                         _stream_ptr(self.device), ctypes.byref(h)), "gt_plan")
+        self.handle = h
+
+    def params(self, i=0):
+        a, b, c, d = (ctypes.c_int32() for _ in range(4))
+        _check(lib().gt_plan_params(self.handle, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                    ctypes.byref(d)), "gt_plan_params")
+        return dict(fine_bits=a.value, digit_bits=b.value, passes=c.value, variant=d.value)
+
+    def alloc_out(self, i=0, payload_dtype=torch.uint32):
+        n, m, pay = self._shapes[i]
+        T = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        S = torch.empty(m, dtype=torch.int32, device=self.device)
+        Q = torch.empty(m, dtype=payload_dtype, device=self.device) if pay else None
+        return T, S, Q
+
+    def run(self, offsets, indices, payload=None, out=None):
+        _check_inputs(offsets, indices, payload)
+        T, S, Q = out if out is not None else self.alloc_out(0, payload.dtype if payload is not None else None)
+        g = _csr(offsets, indices, payload)
+        o = CSC(T.data_ptr(), S.data_ptr() if S.numel() else None,
+                (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
+        _check(lib().gt_transpose(self.handle, ctypes.byref(g), ctypes.byref(o), self.workspace.data_ptr(),
+                                  self.workspace.numel(), _stream_ptr(self.device)), "gt_transpose")
+        return T, S, Q
+
+    def run_batched(self, graphs, outs=None):
+        if outs is None:
+            outs = [self.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(graphs)]
+        arr = (CSR * self.count)(*[_csr(*g) for g in graphs])
+        oarr = (CSC * self.count)(*[CSC(T.data_ptr(), S.data_ptr() if S.numel() else None,
+                                        (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
+                                    for T, S, Q in outs])
+        _check(lib().gt_transpose_batched(self.handle, self.count, arr, oarr, self.workspace.data_ptr(),
+                                          self.workspace.numel(), _stream_ptr(self.device)), "gt_transpose_batched")
+        return outs
+
+    def profile(self, enable=True):
+        _check(lib().gt_profile(self.handle, int(bool(enable))), "gt_profile")
+
+    def profile_read(self, max_kernels=32):
+        """{kernel name: (total ms, launches)} since profiling was enabled or last read."""
+        names = (ctypes.c_char * (32 * max_kernels))()
+        ms = (ctypes.c_double * max_kernels)()
+        nl = (ctypes.c_int32 * max_kernels)()
+        cnt = ctypes.c_int32()
+        _check(lib().gt_profile_read(self.handle, max_kernels, names, ms, nl, ctypes.byref(cnt)),
+               "gt_profile_read")
+        raw = bytes(names)
+        out = {}
+        for k in range(cnt.value):
+            name = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
+            out[name] = (ms[k], nl[k])
+        return out
+
+    def device_status(self):
+        torch.cuda.current_stream(self.device).synchronize()
+        return lib().gt_device_status(self.workspace.data_ptr())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.gt_plan_destroy(h)
+            self.handle = None
+
+
+def transpose(offsets, indices, payload=None, options=None):
+    """Transpose one CSR graph on its GPU; returns (T, S, Q)."""
+    plan = Plan([(offsets, indices, payload)], options)
+    return plan.run(offsets, indices, payload)

@@ -1,0 +1,396 @@
+// C ABI of the transposition library: planning, workspace layout, launch
+// sequence.  See include/gt.h for the contract.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/gt.h"
+#include "gt_internal.h"
+#include "gt_plan.h"
+
+using namespace gt;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int ceil_log2(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << b) < x) ++b;
+  return b;
+}
+
+bool valid_csr_args(const gt_csr_t &g) {
+  if (g.n < 0 || g.m < 0 || g.n > INT32_MAX) return false;
+  if (g.offsets == nullptr) return false;
+  if (g.m > 0 && g.indices == nullptr) return false;
+  if (g.m >= (int64_t(1) << 40)) return false;
+  return true;
+}
+
+}  // namespace
+
+namespace gt {
+
+// Derive passes/shifts/bins from (n, m, fine_bits, digit_bits, variant) and
+// lay out the workspace regions of one graph starting at byte `base`.
+void finalize_params(GraphPlan &p, size_t base) {
+  const int L = std::max(1, ceil_log2(std::max<int64_t>(p.n, 2)));
+  int fb = std::min(p.fine_bits, kMaxFineBits);
+  fb = std::min(fb, L - 1);
+  fb = std::max(fb, 0);
+  p.fine_bits = fb;
+  if (L - fb > kMaxPasses * 10) fb = L - kMaxPasses * 10;  // at most 3 digits of <= 10 bits
+  p.fine_bits = fb;
+  const int dbits = L - fb;  // >= 1
+  int maxb = std::max(1, std::min(p.digit_bits, 10));
+  maxb = std::max(maxb, (dbits + kMaxPasses - 1) / kMaxPasses);  // widen digits rather than add passes
+  p.passes = (dbits + maxb - 1) / maxb;
+  int rem = dbits, shift = fb, maxbits = 0;
+  for (int i = 0; i < p.passes; ++i) {
+    const int b = (rem + (p.passes - i) - 1) / (p.passes - i);
+    p.bits[i] = b;
+    p.shift[i] = shift;
+    shift += b;
+    rem -= b;
+    maxbits = std::max(maxbits, b);
+  }
+  p.max_bits = maxbits;
+  p.total_bits = dbits;
+  p.nbins_total = int64_t(1) << dbits;
+  p.nbins = (p.n + (int64_t(1) << fb) - 1) >> fb;
+  if (p.n == 0) p.nbins = 0;
+  p.tile = lsd_tile_size(p.variant);
+  p.ntiles = (p.m + p.tile - 1) / p.tile;
+
+  size_t off = base;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  p.off_err = 0;  // one status word for the whole workspace (byte 0)
+  p.off_ticket = take(sizeof(uint32_t) * kMaxPasses);
+  p.off_part = take(sizeof(uint32_t) * (size_t)kHistBlocks * kMaxPasses * kMaxRadix);
+  p.off_digit = take(sizeof(uint64_t) * kMaxPasses * (kMaxRadix + 1));
+  p.off_bin = take(sizeof(uint64_t) * (size_t)(p.nbins_total + 1));
+  p.off_status = take(sizeof(uint64_t) * (size_t)p.ntiles * ((size_t)1 << p.max_bits));
+  p.off_tsrc = take(sizeof(int32_t) * (size_t)std::max<int64_t>(p.ntiles, 1));
+  const size_t m = (size_t)p.m;
+  p.off_a_src = p.off_a_key = p.off_a_pay = 0;
+  p.off_a2_src = p.off_a2_key = p.off_a2_pay = 0;
+  if (p.passes >= 2) {
+    p.off_a_src = take(4 * m);
+    p.off_a_key = take(4 * m);
+    if (p.pay) p.off_a_pay = take(4 * m);
+  }
+  if (p.passes >= 3) {
+    p.off_a2_src = take(4 * m);
+    p.off_a2_key = take(4 * m);
+    if (p.pay) p.off_a2_pay = take(4 * m);
+  }
+  p.off_b_src = take(4 * m);
+  p.off_b_key = take(2 * m);
+  p.off_b_pay = p.pay ? take(4 * m) : 0;
+  const size_t nb = (size_t)std::max<int64_t>(p.nbins, 1);
+  p.max_items = p.nbins + (p.m + final_tile_size() - 1) / final_tile_size();
+  p.off_nch = take(4 * nb);
+  p.off_ibase = take(4 * nb);
+  p.off_ibin = take(4 * (size_t)std::max<int64_t>(p.max_items, 1));
+  p.off_itotal = take(4 * 4);
+  p.off_sstatus = take(8 * (size_t)((p.nbins + scan_tile_size() - 1) / scan_tile_size() + 1));
+  p.off_cntab = take(4 * (size_t)std::max<int64_t>(p.max_items, 1) * ((size_t)1 << p.fine_bits));
+  p.max_big = std::min<int64_t>(p.nbins, p.m / final_tile_size() + 1);
+  p.off_big = take(4 * (size_t)std::max<int64_t>(p.max_big, 1));
+  p.ws_end = off;
+}
+
+// Largest workspace any policy can need for one graph.
+size_t graph_workspace_bound(int64_t n, int64_t m, bool pay) {
+  size_t best = 0;
+  for (int fb = 0; fb <= kMaxFineBits; ++fb)
+    for (int variant = 1; variant <= 3; ++variant)
+      for (int db = 4; db <= 10; ++db) {
+        GraphPlan p{};
+        p.n = n; p.m = m; p.pay = pay; p.fine_bits = fb; p.digit_bits = db; p.variant = variant;
+        finalize_params(p, 0);
+        best = std::max(best, p.ws_end);
+      }
+  return best;
+}
+
+hipEvent_t Profiler::get() {
+  if (used == pool.size()) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    pool.push_back(ev);
+  }
+  return pool[used++];
+}
+
+hipError_t Profiler::begin(const char *name, hipStream_t st) {
+  if (!on) return hipSuccess;
+  ProfRec r{name, get(), get()};
+  if (!r.start || !r.stop) return hipErrorOutOfMemory;
+  recs.push_back(r);
+  return hipEventRecord(r.start, st);
+}
+
+hipError_t Profiler::end(hipStream_t st) {
+  if (!on || recs.empty()) return hipSuccess;
+  return hipEventRecord(recs.back().stop, st);
+}
+
+// Enqueue the whole transposition of one graph.
+gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
+                        bool reset_status, Profiler *prof, hipStream_t st) {
+  hipError_t e = hipSuccess;
+#define GT_CHK(x) do { e = (x); if (e != hipSuccess) return GT_ERR_HIP; } while (0)
+#define GT_TIMED(name, x) do { if (prof) GT_CHK(prof->begin(name, st)); GT_CHK(x); if (prof) GT_CHK(prof->end(st)); } while (0)
+  uint32_t *err = reinterpret_cast<uint32_t *>(ws);
+  if (reset_status) GT_CHK(launch_fill(err, 1, 0u, st));
+  if (p.n == 0 || p.m == 0) {
+    // T = 0 everywhere
+    GT_CHK(launch_fill(reinterpret_cast<uint32_t *>(out.offsets), 2 * (uint64_t)(p.n + 1), 0u, st));
+    if (validate && p.n > 0) GT_CHK(launch_validate_offsets(g.offsets, p.n, p.m, err, st));
+    return GT_OK;
+  }
+  if (validate) GT_CHK(launch_validate_offsets(g.offsets, p.n, p.m, err, st));
+
+  uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + p.off_ticket);
+  uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
+  uint64_t *digit = reinterpret_cast<uint64_t *>(ws + p.off_digit);
+  uint64_t *bins = reinterpret_cast<uint64_t *>(ws + p.off_bin);
+  uint64_t *status = reinterpret_cast<uint64_t *>(ws + p.off_status);
+  int32_t *tsrc = reinterpret_cast<int32_t *>(ws + p.off_tsrc);
+
+  HistArgs h{};
+  h.passes = p.passes;
+  for (int i = 0; i < p.passes; ++i) { h.shift[i] = p.shift[i]; h.bits[i] = p.bits[i]; }
+  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, kHistBlocks, part, err, st));
+  GT_TIMED("k_digit_scan", launch_digit_scan(part, kHistBlocks, h, digit, bins, p.nbins_total, p.m, st));
+  GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
+
+  const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * 2;
+  const int32_t *cur_src = nullptr;
+  const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
+  for (int pass = 0; pass < p.passes; ++pass) {
+    const bool first = pass == 0, last = pass == p.passes - 1;
+    GT_TIMED("k_fill_status", launch_fill(reinterpret_cast<uint32_t *>(status), status_words, 0u, st));
+    GT_CHK(launch_fill(ticket + pass, 1, 0u, st));
+    LsdArgs a{};
+    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc;
+    a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
+    if (last) {
+      a.out_src = reinterpret_cast<int32_t *>(ws + p.off_b_src);
+      a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_b_key);
+      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + p.off_b_pay) : nullptr;
+    } else {
+      const bool use_a2 = (pass == 1);
+      a.out_src = reinterpret_cast<int32_t *>(ws + (use_a2 ? p.off_a2_src : p.off_a_src));
+      a.out_key32 = reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_key : p.off_a_key));
+      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_pay : p.off_a_pay)) : nullptr;
+    }
+    a.shift = p.shift[pass];
+    a.bits = p.bits[pass];
+    a.digit_start = digit + pass * (kMaxRadix + 1);
+    a.status = status;
+    a.ticket = ticket + pass;
+    a.m = p.m; a.n = p.n;
+    a.fine_shift = p.fine_bits;
+    a.lower_bits = p.total_bits - p.bits[p.passes - 1];
+    a.fine_mask = (1u << p.fine_bits) - 1u;
+    a.bin_start = bins;
+    static const char *kLsdNames[kMaxPasses] = {"k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2"};
+    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, st));
+    cur_src = a.out_src;
+    cur_key = a.out_key32;
+    cur_pay = a.out_pay;
+  }
+  FinalArgs f{};
+  f.in_src = reinterpret_cast<const int32_t *>(ws + p.off_b_src);
+  f.in_key = reinterpret_cast<const uint16_t *>(ws + p.off_b_key);
+  f.in_pay = p.pay ? reinterpret_cast<const uint32_t *>(ws + p.off_b_pay) : nullptr;
+  f.bin_start = bins;
+  f.T = out.offsets; f.S = out.indices; f.Q = out.payload;
+  f.n = p.n; f.m = p.m; f.nbins = p.nbins; f.fine_bits = p.fine_bits;
+  f.nch = reinterpret_cast<uint32_t *>(ws + p.off_nch);
+  f.item_base = reinterpret_cast<uint32_t *>(ws + p.off_ibase);
+  f.item_bin = reinterpret_cast<uint32_t *>(ws + p.off_ibin);
+  f.total_items = reinterpret_cast<uint32_t *>(ws + p.off_itotal);
+  f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
+  f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
+  f.nbig = f.total_items + 2;
+  uint64_t *sstatus = reinterpret_cast<uint64_t *>(ws + p.off_sstatus);
+  const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
+  GT_TIMED("k_bin_items", launch_bin_items(f, st));
+  GT_CHK(launch_fill(reinterpret_cast<uint32_t *>(sstatus), 2 * (uint64_t)scan_tiles, 0u, st));
+  GT_CHK(launch_fill(f.total_items + 1, 2, 0u, st));  // scan ticket, big-bin count
+  GT_TIMED("k_scan_u32", launch_scan_u32(f.nch, f.item_base, p.nbins, sstatus, f.total_items + 1, f.total_items, st));
+  GT_TIMED("k_item_map", launch_item_map(f, st));
+  GT_TIMED("k_big_count", launch_big_count(f, p.max_items, st));
+  GT_TIMED("k_big_scan", launch_big_scan(f, p.max_big, st));
+  GT_TIMED("k_final", launch_final(f, p.max_items, p.pay, st));
+#undef GT_TIMED
+#undef GT_CHK
+  return GT_OK;
+}
+
+}  // namespace gt
+
+gt_plan_st::~gt_plan_st() {
+  for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+const char *gt_status_string(gt_status s) {
+  switch (s) {
+    case GT_OK: return "ok";
+    case GT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case GT_ERR_INVALID_GRAPH: return "invalid graph";
+    case GT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case GT_ERR_UNSUPPORTED: return "unsupported parameters";
+    case GT_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out) {
+  if (graphs == nullptr || count <= 0 || bytes_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  size_t total = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+    total += align_up(graph_workspace_bound(graphs[i].n, graphs[i].m, graphs[i].payload != nullptr));
+  }
+  total += kAlign;  // status word
+  total += align_up(plan_scratch_bytes(graphs, count));
+  *bytes_out = total;
+  return GT_OK;
+}
+
+gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
+                  size_t workspace_bytes, void *stream, gt_plan_t *plan_out) {
+  if (graphs == nullptr || count <= 0 || plan_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  for (int32_t i = 0; i < count; ++i)
+    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+  gt_options_t o{};
+  if (opt) o = *opt;
+  if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_TABLE) return GT_ERR_INVALID_ARGUMENT;
+  if (o.policy == GT_POLICY_FIXED) {
+    if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
+        (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 3)
+      return GT_ERR_UNSUPPORTED;
+  }
+  gt_plan_st *plan = new (std::nothrow) gt_plan_st();
+  if (!plan) return GT_ERR_INVALID_ARGUMENT;
+  plan->count = count;
+  plan->validate = o.validate != 0;
+  plan->graphs.resize(count);
+  gt_status st = choose_params(plan, graphs, count, o, workspace, workspace_bytes, (hipStream_t)stream);
+  if (st != GT_OK) { delete plan; return st; }
+  size_t base = kAlign;  // byte 0: device status word
+  for (int32_t i = 0; i < count; ++i) {
+    GraphPlan &p = plan->graphs[i];
+    finalize_params(p, base);
+    base = align_up(p.ws_end);
+  }
+  plan->ws_bytes = std::max<size_t>(base, 256);
+  *plan_out = plan;
+  return GT_OK;
+}
+
+static gt_status check_io(const GraphPlan &p, const gt_csr_t *g, const gt_csc_t *out) {
+  if (g == nullptr || out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  if (!valid_csr_args(*g)) return GT_ERR_INVALID_ARGUMENT;
+  if (g->n != p.n || g->m != p.m || (g->payload != nullptr) != p.pay) return GT_ERR_INVALID_ARGUMENT;
+  if (out->offsets == nullptr || (p.m > 0 && out->indices == nullptr)) return GT_ERR_INVALID_ARGUMENT;
+  if ((out->payload != nullptr) != p.pay) return GT_ERR_INVALID_ARGUMENT;
+  return GT_OK;
+}
+
+gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t workspace_bytes,
+                       void *stream) {
+  if (plan == nullptr || plan->count != 1 || workspace == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  const GraphPlan &p = plan->graphs[0];
+  gt_status s = check_io(p, g, out);
+  if (s != GT_OK) return s;
+  if (workspace_bytes < plan->ws_bytes) return GT_ERR_WORKSPACE_TOO_SMALL;
+  return enqueue_graph(p, *g, *out, static_cast<char *>(workspace), plan->validate, true, &plan->prof,
+                       (hipStream_t)stream);
+}
+
+gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+  if (plan == nullptr || graphs == nullptr || outs == nullptr || workspace == nullptr || count != plan->count)
+    return GT_ERR_INVALID_ARGUMENT;
+  for (int32_t i = 0; i < count; ++i) {
+    gt_status s = check_io(plan->graphs[i], &graphs[i], &outs[i]);
+    if (s != GT_OK) return s;
+  }
+  if (workspace_bytes < plan->ws_bytes) return GT_ERR_WORKSPACE_TOO_SMALL;
+  return enqueue_batched(plan, graphs, outs, static_cast<char *>(workspace), (hipStream_t)stream);
+}
+
+gt_status gt_device_status(const void *workspace) {
+  if (workspace == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  uint32_t err = 0;
+  if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return GT_ERR_HIP;
+  return err ? GT_ERR_INVALID_GRAPH : GT_OK;
+}
+
+gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits, int32_t *passes,
+                         int32_t *variant) {
+  if (plan == nullptr || i < 0 || i >= plan->count) return GT_ERR_INVALID_ARGUMENT;
+  const GraphPlan &p = plan->graphs[i];
+  if (fine_bits) *fine_bits = p.fine_bits;
+  if (digit_bits) *digit_bits = p.max_bits;
+  if (passes) *passes = p.passes;
+  if (variant) *variant = p.variant;
+  return GT_OK;
+}
+
+gt_status gt_plan_destroy(gt_plan_t plan) {
+  delete plan;
+  return GT_OK;
+}
+
+gt_status gt_profile(gt_plan_t plan, int32_t enable) {
+  if (plan == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  plan->prof.on = enable != 0;
+  plan->prof.recs.clear();
+  plan->prof.used = 0;
+  return GT_OK;
+}
+
+gt_status gt_profile_read(gt_plan_t plan, int32_t max_kernels, char (*names)[32], double *total_ms,
+                          int32_t *launches, int32_t *count_out) {
+  if (plan == nullptr || count_out == nullptr || (max_kernels > 0 && (!names || !total_ms || !launches)))
+    return GT_ERR_INVALID_ARGUMENT;
+  int32_t count = 0;
+  for (const ProfRec &r : plan->prof.recs) {
+    if (hipEventSynchronize(r.stop) != hipSuccess) return GT_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return GT_ERR_HIP;
+    int32_t k = 0;
+    while (k < count && strncmp(names[k], r.name, 31) != 0) ++k;
+    if (k == count) {
+      if (count >= max_kernels) continue;
+      strncpy(names[k], r.name, 31);
+      names[k][31] = 0;
+      total_ms[k] = 0.0;
+      launches[k] = 0;
+      ++count;
+    }
+    total_ms[k] += ms;
+    launches[k] += 1;
+  }
+  plan->prof.recs.clear();
+  plan->prof.used = 0;
+  *count_out = count;
+  return GT_OK;
+}
+
+}  // extern "C"

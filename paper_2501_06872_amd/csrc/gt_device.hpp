@@ -1,0 +1,162 @@
+// Device helpers shared by the transposition kernels (wave64, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
+
+// Lanes of the wave whose `key` equals this lane's key, among `active` lanes.
+// One ballot per key bit; keys must be < 2^BITS.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_peers(uint32_t key, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = (key >> b) & 1u;
+    const uint64_t ones = __ballot(bit);
+    peers &= bit ? ones : ~ones;
+  }
+  return peers;
+}
+
+// Stable in-wave ranking of one row of keys (< 2^bits) through LDS.
+// Each lane ORs its lane bit into tab[key] (a per-wave table of 64-bit lane
+// masks, zero between rows), so reading tab[key] back yields the lanes holding
+// the same key.  The rank is the wave's running count of the key (wcnt, read
+// before the lowest such lane advances it) plus the number of lower lanes
+// with the key; the lowest lane then advances the count and clears the slot.
+// LDS instructions of one wave execute in order, so no barrier is needed.
+__device__ __forceinline__ uint32_t rank_row_lds(uint32_t key, bool ok, uint16_t *wcnt,
+                                                 unsigned long long *tab, int lane) {
+  const unsigned long long bit = 1ull << lane, lt = bit - 1ull;
+  if (ok) atomicOr(&tab[key], bit);
+  __builtin_amdgcn_wave_barrier();
+  const unsigned long long peers = ok ? tab[key] : 0ull;
+  const uint32_t old = ok ? (uint32_t)wcnt[key] : 0u;
+  __builtin_amdgcn_wave_barrier();
+  if (ok && (peers & lt) == 0ull) {
+    wcnt[key] = (uint16_t)(old + (uint32_t)__popcll(peers));
+    tab[key] = 0ull;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return old + (uint32_t)__popcll(peers & lt);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v = v > t ? v : t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_sum64(uint64_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint64_t t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive prefix sum of s[0..len) in LDS, in place; returns the total.
+// NT threads; len <= 4 * NT.  `wsum` is scratch of NT/64 entries.
+template <int NT, typename T>
+__device__ T block_excl_scan(T *s, int len, T *wsum) {
+  constexpr int NW = NT / kWave;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int per = (len + NT - 1) / NT;
+  const int beg = tid * per;
+  T local = 0;
+  for (int k = 0; k < per; ++k)
+    if (beg + k < len) local += s[beg + k];
+  T incl = local;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    T run = 0;
+    for (int i = 0; i < NW; ++i) { T c = wsum[i]; wsum[i] = run; run += c; }
+    wsum[NW] = run;
+  }
+  __syncthreads();
+  T run = wsum[w] + incl - local;
+  for (int k = 0; k < per; ++k)
+    if (beg + k < len) { T c = s[beg + k]; s[beg + k] = run; run += c; }
+  T total = wsum[NW];
+  __syncthreads();
+  return total;
+}
+
+// Status word of the decoupled look-back (Merrill & Garland 2016):
+// bits 63..62 flag (0 = not yet published, 1 = tile aggregate, 2 = inclusive
+// prefix), bits 61..0 the count.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of this tile's `count` over all earlier tiles of the same
+// column (`stride` = number of columns); publishes aggregate, then inclusive.
+// Predecessors are read in windows of kLookWin independent loads, so one
+// round trip covers several tiles of the chain.
+constexpr int kLookWin = 8;
+__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *status, int64_t tile, int64_t stride,
+                                                      int64_t col, uint64_t count) {
+  uint64_t *mine = status + tile * stride + col;
+  if (tile == 0) {
+    status_store(mine, kFlagIncl | count);
+    return 0;
+  }
+  status_store(mine, kFlagAgg | count);
+  uint64_t excl = 0;
+  int64_t t = tile - 1;
+  bool done = false;
+  while (!done) {
+    uint64_t s[kLookWin];
+#pragma unroll
+    for (int k = 0; k < kLookWin; ++k) s[k] = (t - k >= 0) ? status_load(status + (t - k) * stride + col) : kFlagIncl;
+#pragma unroll
+    for (int k = 0; k < kLookWin; ++k) {
+      if (!done) {
+        const uint64_t *p = status + (t - k) * stride + col;
+        while ((s[k] >> 62) == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          s[k] = status_load(p);
+        }
+        excl += s[k] & kValueMask;
+        if ((s[k] >> 62) == 2) done = true;
+      }
+    }
+    t -= kLookWin;
+  }
+  status_store(mine, kFlagIncl | (excl + count));
+  return excl;
+}
+
+}  // namespace gt

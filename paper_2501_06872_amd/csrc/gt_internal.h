@@ -1,0 +1,90 @@
+// Internal interface between the C ABI (gt_api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+constexpr int kMaxPasses = 3;
+constexpr int kMaxRadix = 1024;   // digit width <= 10 bits
+constexpr int kMaxFineBits = 9;   // bins of <= 512 destinations in k_final
+constexpr int kHistBlocks = 512;
+
+constexpr uint32_t kErrBadIndex = 1u;
+constexpr uint32_t kErrBadOffsets = 2u;
+
+struct HistArgs {
+  int passes;
+  int shift[kMaxPasses];
+  int bits[kMaxPasses];
+};
+
+struct LsdArgs {
+  // CSR input (first pass)
+  const int64_t *O;
+  const int32_t *D;
+  const uint32_t *P;
+  const int32_t *tile_src0;
+  // partitioned input (later passes)
+  const int32_t *in_src;
+  const uint32_t *in_key;
+  const uint32_t *in_pay;
+  // output
+  int32_t *out_src;
+  uint32_t *out_key32;
+  uint16_t *out_key16;
+  uint32_t *out_pay;
+  // digit of this pass: (key >> shift) & ((1 << bits) - 1)
+  int shift, bits;
+  const uint64_t *digit_start;
+  uint64_t *status;
+  uint32_t *ticket;
+  int64_t m, n;
+  // last pass: bin bookkeeping
+  int fine_shift;    // = fine bits
+  int lower_bits;    // digit bits of the earlier passes
+  uint32_t fine_mask;
+  uint64_t *bin_start;
+};
+
+struct FinalArgs {
+  const int32_t *in_src;
+  const uint16_t *in_key;
+  const uint32_t *in_pay;
+  const uint64_t *bin_start;
+  int64_t *T;
+  int32_t *S;
+  uint32_t *Q;
+  int64_t n, m, nbins;
+  int fine_bits;
+  // work items: bins longer than one tile are split into tile-sized chunks
+  uint32_t *nch;          // [nbins] chunks per bin
+  uint32_t *item_base;    // [nbins] first item of each bin
+  uint32_t *item_bin;     // [max items] bin of each item
+  uint32_t *total_items;  // device scalar
+  uint32_t *cntab;        // [max items][2^fine_bits] per-chunk vertex counts -> prefixes
+  uint32_t *bigbins;      // [max big bins] bins split into several chunks
+  uint32_t *nbig;         // device scalar
+};
+
+int64_t lsd_tile_size(int variant);
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st);
+int64_t final_tile_size();
+int64_t scan_tile_size();
+hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st);
+hipError_t launch_item_map(const FinalArgs &a, hipStream_t st);
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint64_t *status, uint32_t *ticket,
+                           uint32_t *total, hipStream_t st);
+hipError_t launch_big_count(const FinalArgs &a, int64_t max_items, hipStream_t st);
+hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st);
+hipError_t launch_final(const FinalArgs &a, int64_t max_items, bool pay, hipStream_t st);
+hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err, hipStream_t st);
+hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile, int64_t ntiles, int32_t *out,
+                           hipStream_t st);
+hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int nblocks, uint32_t *part,
+                       uint32_t *err, hipStream_t st);
+hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *digit_start,
+                             uint64_t *bin_start, int64_t nbins_total, int64_t m, hipStream_t st);
+
+}  // namespace gt

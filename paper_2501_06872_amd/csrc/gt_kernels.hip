@@ -1,0 +1,723 @@
+// Kernels of the stable CSR -> CSC transposition.
+//
+// The paper's three steps (Algorithm 2: count degrees, aggregate counters,
+// write edges) are kept, but every counter lives in LDS and no edge ever
+// touches a global atomic:
+//
+//  k_hist      Step 1.  One streaming read of the CSR edges; per-workgroup
+//              LDS histograms of the destination digits used by the
+//              partition passes (plus index validation).
+//  k_digit_scan Step 2 at digit granularity: exclusive scan of the digit
+//              totals -> start of every digit in the partitioned stream.
+//  k_lsd       Step 3, part 1.  Stable partition of the edge stream by one
+//              destination digit (least significant digit first), tile by
+//              tile: coalesced loads, in-wave stable ranking by ballot
+//              matching, per-wave LDS counters, decoupled look-back across
+//              tiles for the per-digit prefix, LDS-staged coalesced writes.
+//              The first pass reads the CSR and derives each edge's source
+//              from the offsets slice staged in LDS; the last pass also
+//              records where every fine vertex bin starts.
+//  k_final     Step 3, part 2.  One workgroup per bin of 2^fine_bits
+//              destinations: per-vertex in-degrees counted in LDS, exclusive
+//              scan -> CSC offsets of the bin, stable placement of the bin's
+//              edges (ascending source) through LDS, coalesced write-out.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gt_device.hpp"
+#include "gt_internal.h"
+
+namespace gt {
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t s = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += s) p[i] = v;
+}
+
+// Offsets validation: O[0] = 0, nondecreasing, O[n] = m.
+__global__ void k_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  if (i == 0) bad = (O[0] != 0) || (O[n] != m);
+  for (; i < n; i += s)
+    if (O[i + 1] < O[i]) bad = true;
+  if (bad) atomicOr(err, kErrBadOffsets);
+}
+
+// Source of the first edge of every tile: the largest u with O[u] <= tile_base.
+__global__ void k_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile_size, int64_t ntiles,
+                           int32_t *out) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int64_t base = t * tile_size;
+  int64_t lo = 0, hi = n;  // invariant: O[lo] <= base (when valid); answer in [lo, hi)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (O[mid] <= base) lo = mid; else hi = mid;
+  }
+  (void)m;
+  out[t] = (int32_t)lo;
+}
+
+// Step 1: digit histograms of the destinations, one LDS histogram per pass
+// and per wave (fewer same-address LDS conflicts on skewed digits).  Partial
+// histograms are written per workgroup (no global atomics) and summed by
+// k_digit_scan.
+template <int PASSES>
+__global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int64_t m, int64_t n, HistArgs h,
+                                              uint32_t *__restrict__ part, uint32_t *err) {
+  constexpr int NW = 4;
+  __shared__ uint32_t s_h[NW][PASSES * kMaxRadix];
+  const int tid = threadIdx.x, w = tid / kWave;
+  for (int i = tid; i < NW * PASSES * kMaxRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t *hw = s_h[w];
+  int sh[PASSES];
+  uint32_t mk[PASSES];
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) { sh[p] = h.shift[p]; mk[p] = (1u << h.bits[p]) - 1u; }
+  bool bad = false;
+  const uint32_t un = (uint32_t)(n > 0xFFFFFFFFll ? 0xFFFFFFFFll : n);
+  auto count = [&](uint32_t u) {
+    bad |= u >= un;  // also catches negative indices
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) atomicAdd(&hw[p * kMaxRadix + ((u >> sh[p]) & mk[p])], 1u);
+  };
+  const int64_t nvec = m >> 2;
+  const uint4 *D4 = reinterpret_cast<const uint4 *>(D);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid; i < nvec; i += stride) {
+    const uint4 q = D4[i];
+    count(q.x); count(q.y); count(q.z); count(q.w);
+  }
+  for (int64_t i = (nvec << 2) + blockIdx.x * (int64_t)blockDim.x + tid; i < m; i += stride) count((uint32_t)D[i]);
+  if (bad) atomicOr(err, kErrBadIndex);
+  __syncthreads();
+  uint32_t *out = part + (int64_t)blockIdx.x * kMaxPasses * kMaxRadix;
+  for (int i = tid; i < PASSES * kMaxRadix; i += blockDim.x) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) c += s_h[x][i];
+    out[i] = c;
+  }
+}
+
+// Step 2 (digit level): sum the partial histograms, exclusive scan per pass.
+// One workgroup per pass.  Also initialises the look-back tickets and the
+// terminal bin start.
+__global__ __launch_bounds__(1024) void k_digit_scan(const uint32_t *__restrict__ part, int nblocks, HistArgs h,
+                                                     uint64_t *digit_start, uint64_t *bin_start,
+                                                     int64_t nbins_total, int64_t m) {
+  __shared__ uint64_t s_tot[kMaxRadix];
+  __shared__ uint64_t s_wsum[1024 / kWave + 1];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int radix = 1 << h.bits[p];
+  for (int d = tid; d < radix; d += blockDim.x) {
+    uint64_t s = 0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kMaxPasses * kMaxRadix + p * kMaxRadix + d];
+    s_tot[d] = s;
+  }
+  __syncthreads();
+  block_excl_scan<1024, uint64_t>(s_tot, radix, s_wsum);
+  for (int d = tid; d < radix; d += blockDim.x) digit_start[p * (kMaxRadix + 1) + d] = s_tot[d];
+  if (tid == 0) digit_start[p * (kMaxRadix + 1) + radix] = (uint64_t)m;
+  if (p == 0 && tid == 0) bin_start[nbins_total] = (uint64_t)m;
+}
+
+// ---------------------------------------------------------------------------
+// k_lsd: one stable partition pass by a destination digit.
+// ---------------------------------------------------------------------------
+template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST>
+__global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
+  constexpr int NT = WAVES * kWave;
+  constexpr int TILE = NT * ITEMS;
+  constexpr int RADIX = 1 << RBITS;
+  // staging buffer; during ranking it holds the per-wave lane-mask tables
+  constexpr int STAGE_WORDS = TILE > 2 * WAVES * RADIX ? TILE : 2 * WAVES * RADIX;
+  __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
+  __shared__ uint16_t s_wcnt[WAVES][RADIX];
+  __shared__ uint32_t s_tot[RADIX];
+  __shared__ uint32_t s_toff[RADIX];
+  __shared__ uint64_t s_gbase[RADIX];
+  __shared__ uint32_t s_misc[NT / kWave + 1];
+  __shared__ int64_t s_tile;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int radix = 1 << a.bits;
+  const uint32_t dmask = (uint32_t)radix - 1u;
+
+  for (int i = tid; i < WAVES * RADIX; i += NT) (&s_wcnt[0][0])[i] = 0;
+  for (int i = tid; i < 2 * WAVES * RADIX; i += NT) s_stage[i] = 0u;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t base = tile * TILE;
+  const int64_t cnt64 = a.m - base < TILE ? a.m - base : TILE;
+  const int cnt = (int)cnt64;
+  // rows of 64 consecutive edges; wave w owns rows [w*ITEMS, (w+1)*ITEMS)
+  auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
+
+  // Keys only; sources and payload are loaded when they are staged.
+  uint32_t key[ITEMS];
+  {
+    const uint32_t *kin = CSR_IN ? reinterpret_cast<const uint32_t *>(a.D) + base : a.in_key + base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? kin[row_idx(j)] : 0u;
+  }
+
+  // In-wave stable ranking: rows in edge order, peers matched through LDS.
+  uint32_t lpos[ITEMS];
+  {
+    unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * RADIX;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      lpos[j] = rank_row_lds((key[j] >> a.shift) & dmask, row_idx(j) < cnt, s_wcnt[w], tab, lane);
+  }
+  __syncthreads();
+
+  // per digit: tile total, and exclusive prefix over waves (in place)
+  for (int d = tid; d < radix; d += NT) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      const uint32_t c = s_wcnt[x][d];
+      s_wcnt[x][d] = (uint16_t)run;
+      run += c;
+    }
+    s_tot[d] = run;
+    s_toff[d] = run;
+  }
+  __syncthreads();
+  // look-back per digit across tiles
+  for (int d = tid; d < radix; d += NT) {
+    const uint64_t excl = lookback_exclusive(a.status, tile, radix, d, s_tot[d]);
+    s_gbase[d] = a.digit_start[d] + excl;
+  }
+  block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets
+
+  // stage keys in sorted order
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (row_idx(j) < cnt) {
+      const uint32_t d = (key[j] >> a.shift) & dmask;
+      lpos[j] += s_toff[d] + s_wcnt[w][d];
+      s_stage[lpos[j]] = key[j];
+    }
+  }
+  __syncthreads();
+
+  // write keys; remember each output slot's digit (two per register)
+  uint32_t dpk[(ITEMS + 1) / 2];
+#pragma unroll
+  for (int k = 0; k < (ITEMS + 1) / 2; ++k) dpk[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int i = k * NT + tid;
+    if (i < cnt) {
+      const uint32_t kv = s_stage[i];
+      const uint32_t d = (kv >> a.shift) & dmask;
+      dpk[k >> 1] |= d << ((k & 1) * 16);
+      const uint64_t gp = s_gbase[d] + (uint64_t)(i - (int)s_toff[d]);
+      if (LAST) a.out_key16[gp] = (uint16_t)(kv & a.fine_mask);
+      else a.out_key32[gp] = kv;
+    }
+  }
+  auto gpos_of = [&](int k, int i) -> uint64_t {
+    const uint32_t d = (dpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
+    return s_gbase[d] + (uint64_t)(i - (int)s_toff[d]);
+  };
+
+  if (LAST) {
+    // Bin starts.  The tile owns the fine bins whose lower part fl lies in
+    // (fl of the previous tile's last edge, fl of this tile's last edge]; for
+    // every digit d the bin (d, fl) starts after the tile's edges of digit d
+    // with a smaller lower part (edges of one digit are staged sorted by fl).
+    const uint32_t lmask = (1u << a.lower_bits) - 1u;
+    auto fl_of = [&](uint32_t kv) -> uint32_t { return (kv >> a.fine_shift) & lmask; };
+    int64_t fl_prev = -1;
+    if (tile > 0) fl_prev = CSR_IN ? (int64_t)fl_of((uint32_t)a.D[base - 1]) : (int64_t)fl_of(a.in_key[base - 1]);
+    int64_t fl_hi;
+    if (base + cnt64 >= a.m) fl_hi = (int64_t)lmask;
+    else fl_hi = CSR_IN ? (int64_t)fl_of((uint32_t)a.D[base + cnt64 - 1]) : (int64_t)fl_of(a.in_key[base + cnt64 - 1]);
+    const int64_t nown = fl_hi - fl_prev;
+    for (int64_t q = tid; q < nown * radix; q += NT) {
+      const uint32_t fl = (uint32_t)(fl_prev + 1 + q / radix);
+      const uint32_t d = (uint32_t)(q % radix);
+      int lo = (int)s_toff[d], hi = lo + (int)s_tot[d];
+      while (lo < hi) {  // first staged edge of digit d with fl >= target
+        const int mid = (lo + hi) >> 1;
+        if (fl_of(s_stage[mid]) < fl) lo = mid + 1; else hi = mid;
+      }
+      a.bin_start[((uint64_t)d << a.lower_bits) | fl] = s_gbase[d] + (uint64_t)(lo - (int)s_toff[d]);
+    }
+  }
+  __syncthreads();
+
+  // sources
+  {
+    uint32_t src[ITEMS];
+    if (CSR_IN) {
+      // mark the first edge of every source that starts inside the tile, then
+      // fill forward (sources increase along the edge array)
+      for (int i = tid; i < TILE; i += NT) s_stage[i] = 0;
+      __syncthreads();
+      const int64_t u0 = a.tile_src0[tile];
+      if (tid == 0) s_stage[0] = (uint32_t)u0;
+      for (int64_t u = u0 + 1 + tid; u < a.n; u += NT) {
+        const int64_t o = a.O[u];
+        if (o >= base + cnt64) break;
+        if (o > base) atomicMax(&s_stage[o - base], (uint32_t)u);
+      }
+      __syncthreads();
+      uint32_t carry = 0;
+      for (int r = 0; r < ITEMS; ++r) {
+        const int i = (w * ITEMS + r) * kWave + lane;
+        uint32_t v = wave_incl_max(s_stage[i], lane);
+        v = v > carry ? v : carry;
+        s_stage[i] = v;
+        carry = __shfl(v, kWave - 1);
+      }
+      if (lane == 0) s_misc[w] = carry;
+      __syncthreads();
+      uint32_t before = 0;
+      for (int i = 0; i < w; ++i) before = before > s_misc[i] ? before : s_misc[i];
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t v = s_stage[row_idx(j)];
+        src[j] = v > before ? v : before;
+      }
+      __syncthreads();
+    } else {
+      const int32_t *sin = a.in_src + base;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)sin[row_idx(j)] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int i = k * NT + tid;
+    if (i < cnt) a.out_src[gpos_of(k, i)] = (int32_t)s_stage[i];
+  }
+  if (PAY) {
+    uint32_t pay[ITEMS];
+    const uint32_t *pin = CSR_IN ? a.P + base : a.in_pay + base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) pay[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (row_idx(j) < cnt) s_stage[lpos[j]] = pay[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int i = k * NT + tid;
+      if (i < cnt) a.out_pay[gpos_of(k, i)] = s_stage[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic exclusive scan of a u32 array (decoupled look-back over tiles).
+// ---------------------------------------------------------------------------
+template <int NT, int ITEMS>
+__global__ __launch_bounds__(NT) void k_scan_u32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                 int64_t len, uint64_t *status, uint32_t *ticket, uint32_t *total) {
+  constexpr int TILE = NT * ITEMS;
+  __shared__ uint32_t s_w[NT / kWave + 1];
+  __shared__ int64_t s_tile;
+  __shared__ uint64_t s_excl;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t base = tile * TILE + (int64_t)tid * ITEMS;
+  uint32_t v[ITEMS];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    v[k] = (base + k < len) ? in[base + k] : 0u;
+    local += v[k];
+  }
+  const uint32_t incl = wave_incl_sum(local, lane);
+  if (lane == kWave - 1) s_w[w] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < NT / kWave; ++i) { const uint32_t c = s_w[i]; s_w[i] = run; run += c; }
+    s_w[NT / kWave] = run;
+    s_excl = lookback_exclusive(status, tile, 1, 0, run);
+    if ((tile + 1) * TILE >= len) *total = (uint32_t)(s_excl + run);
+  }
+  __syncthreads();
+  uint32_t run = (uint32_t)s_excl + s_w[w] + incl - local;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (base + k < len) { out[base + k] = run; run += v[k]; }
+}
+
+// Per bin: number of work items of k_final (bins longer than one tile are
+// split into tile-sized chunks).  Also writes T[n] = m.
+__global__ void k_bin_items(const uint64_t *bin_start, int64_t nbins, int64_t tile, uint32_t *nch, int64_t *T,
+                            int64_t n, int64_t m) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nbins) return;
+  const uint64_t N = bin_start[f + 1] - bin_start[f];
+  nch[f] = N > (uint64_t)tile ? (uint32_t)((N + tile - 1) / tile) : 1u;
+  if (f == nbins - 1) T[n] = m;
+}
+
+// Item -> bin map, and the list of bins split into several chunks (its order
+// is irrelevant: every big bin is processed independently).
+__global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, int64_t nbins, uint32_t *item_bin,
+                           uint32_t *bigbins, uint32_t *nbig) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nbins) return;
+  const uint32_t b = item_base[f], c = nch[f];
+  for (uint32_t k = 0; k < c; ++k) item_bin[b + k] = (uint32_t)f;
+  if (c > 1) bigbins[atomicAdd(nbig, 1u)] = (uint32_t)f;
+}
+
+// In-wave stable ranking of one row of keys (< 2^BITS) against per-wave LDS
+// counters; returns the rank of this lane's key within the wave's stream.
+template <int BITS>
+__device__ __forceinline__ uint32_t rank_row(uint32_t key, bool ok, uint16_t *wcnt, uint64_t ltmask, int lane) {
+  const uint64_t active = __ballot(ok);
+  const uint64_t peers = match_peers<BITS>(key, active);
+  const int leader = peers ? (__ffsll((unsigned long long)peers) - 1) : lane;
+  uint32_t old = 0;
+  if (ok && lane == leader) {
+    old = wcnt[key];
+    wcnt[key] = (uint16_t)(old + __popcll(peers));
+  }
+  old = __shfl(old, leader);
+  return old + __popcll(peers & ltmask);
+}
+
+// Big bins: in-degree of every vertex of the bin within each chunk.
+template <int WAVES, int ITEMS, int FBITS>
+__global__ __launch_bounds__(WAVES *kWave) void k_big_count(FinalArgs a) {
+  constexpr int NT = WAVES * kWave;
+  constexpr int TILE = NT * ITEMS;
+  constexpr int FW = 1 << FBITS;
+  __shared__ uint32_t s_cnt[FW];
+  const int64_t item = blockIdx.x;
+  if (item >= (int64_t)*a.total_items) return;
+  const uint32_t f = a.item_bin[item];
+  const uint32_t nch = a.nch[f];
+  if (nch == 1) return;
+  const int tid = threadIdx.x;
+  const int fw = 1 << a.fine_bits;
+  const uint32_t vmask = (uint32_t)fw - 1u;
+  const uint32_t first_item = a.item_base[f];
+  const uint64_t bs = a.bin_start[f], be = a.bin_start[f + 1];
+  const uint64_t cb = bs + (uint64_t)(item - first_item) * TILE;
+  const int cnt = (int)((be - cb) < (uint64_t)TILE ? (be - cb) : (uint64_t)TILE);
+  for (int v = tid; v < fw; v += NT) s_cnt[v] = 0;
+  __syncthreads();
+  const uint16_t *keys = a.in_key + cb;
+  for (int i = tid; i < cnt; i += NT) atomicAdd(&s_cnt[keys[i] & vmask], 1u);
+  __syncthreads();
+  uint32_t *row = a.cntab + (uint64_t)item * fw;
+  for (int v = tid; v < fw; v += NT) row[v] = s_cnt[v];
+}
+
+// Big bins, after k_big_count: per-vertex exclusive prefix over the bin's
+// chunks (in place) and the bin's CSC offsets.  One workgroup per big bin.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_big_scan(FinalArgs a) {
+  __shared__ uint64_t s_tot[1 << kMaxFineBits];
+  __shared__ uint64_t s_w64[NT / kWave + 1];
+  if ((int64_t)blockIdx.x >= (int64_t)*a.nbig) return;
+  const uint32_t f = a.bigbins[blockIdx.x];
+  const uint32_t nch = a.nch[f];
+  const uint32_t first_item = a.item_base[f];
+  const int tid = threadIdx.x;
+  const int fw = 1 << a.fine_bits;
+  constexpr int B = 16;
+  for (int v = tid; v < fw; v += NT) {
+    uint64_t run = 0;
+    for (uint32_t k0 = 0; k0 < nch; k0 += B) {
+      uint32_t c[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) c[k] = (k0 + k < nch) ? a.cntab[(uint64_t)(first_item + k0 + k) * fw + v] : 0u;
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        if (k0 + k < nch) {
+          a.cntab[(uint64_t)(first_item + k0 + k) * fw + v] = (uint32_t)run;
+          run += c[k];
+        }
+    }
+    s_tot[v] = run;
+  }
+  __syncthreads();
+  block_excl_scan<NT, uint64_t>(s_tot, fw, s_w64);
+  const uint64_t bs = a.bin_start[f];
+  const int64_t v0 = (int64_t)f << a.fine_bits;
+  for (int v = tid; v < fw; v += NT)
+    if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_tot[v]);
+}
+
+// ---------------------------------------------------------------------------
+// k_final: stable placement of one work item (a whole small bin, or one
+// tile-sized chunk of a big bin) -> CSC sources/payload (+ offsets of small
+// bins).
+// ---------------------------------------------------------------------------
+template <int WAVES, int ITEMS, int FBITS, bool PAY>
+__global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
+  constexpr int NT = WAVES * kWave;
+  constexpr int TILE = NT * ITEMS;
+  constexpr int FW = 1 << FBITS;
+  constexpr int STAGE_WORDS = TILE > 2 * WAVES * FW ? TILE : 2 * WAVES * FW;
+  __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
+  __shared__ uint16_t s_wcnt[WAVES][FW];
+  __shared__ uint32_t s_tot[FW];
+  __shared__ uint32_t s_toff[FW];
+  __shared__ uint64_t s_cur[FW];
+  __shared__ uint32_t s_w32[NT / kWave + 1];
+
+  const int64_t item = blockIdx.x;
+  if (item >= (int64_t)*a.total_items) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const uint32_t f = a.item_bin[item];
+  const uint32_t nch = a.nch[f];
+  const int fw = 1 << a.fine_bits;
+  const uint32_t vmask = (uint32_t)fw - 1u;
+  const uint64_t bs = a.bin_start[f], be = a.bin_start[f + 1];
+  const uint64_t cb = bs + (uint64_t)(item - a.item_base[f]) * TILE;
+  const int cnt = (int)((be - cb) < (uint64_t)TILE ? (be - cb) : (uint64_t)TILE);
+  const int64_t v0 = (int64_t)f << a.fine_bits;
+  auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
+
+  for (int i = tid; i < WAVES * FW; i += NT) (&s_wcnt[0][0])[i] = 0;
+  for (int i = tid; i < 2 * WAVES * FW; i += NT) s_stage[i] = 0u;
+  if (nch > 1) {
+    const uint32_t *row = a.cntab + (uint64_t)item * fw;
+    for (int v = tid; v < fw; v += NT) s_cur[v] = (uint64_t)a.T[v0 + v < a.n ? v0 + v : a.n] + row[v];
+  }
+  __syncthreads();
+  uint32_t key[ITEMS], lpos[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? (uint32_t)(a.in_key[cb + row_idx(j)] & vmask) : 0u;
+  {
+    unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FW;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) lpos[j] = rank_row_lds(key[j], row_idx(j) < cnt, s_wcnt[w], tab, lane);
+  }
+  __syncthreads();
+  for (int v = tid; v < fw; v += NT) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      const uint32_t c = s_wcnt[x][v];
+      s_wcnt[x][v] = (uint16_t)run;
+      run += c;
+    }
+    s_tot[v] = run;
+    s_toff[v] = run;
+  }
+  __syncthreads();
+  block_excl_scan<NT, uint32_t>(s_toff, fw, s_w32);
+  if (nch == 1) {
+    // a whole bin: its counts are the in-degrees of its vertices
+    for (int v = tid; v < fw; v += NT) {
+      s_cur[v] = bs + s_toff[v];
+      if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_toff[v]);
+    }
+    __syncthreads();
+  }
+  if (cnt == 0) return;
+  // the local sorted position of every edge of this thread
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (row_idx(j) < cnt) lpos[j] += s_toff[key[j]] + s_wcnt[w][key[j]];
+  // stage the destination of every sorted slot, then the sources
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (row_idx(j) < cnt) s_stage[lpos[j]] = key[j];
+  __syncthreads();
+  uint32_t vpk[(ITEMS + 1) / 2];
+#pragma unroll
+  for (int k = 0; k < (ITEMS + 1) / 2; ++k) vpk[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int i = k * NT + tid;
+    if (i < cnt) vpk[k >> 1] |= s_stage[i] << ((k & 1) * 16);
+  }
+  auto gpos_of = [&](int k, int i) -> uint64_t {
+    const uint32_t v = (vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
+    return s_cur[v] + (uint64_t)(i - (int)s_toff[v]);
+  };
+  {
+    uint32_t src[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)a.in_src[cb + row_idx(j)] : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int i = k * NT + tid;
+    if (i < cnt) a.S[gpos_of(k, i)] = (int32_t)s_stage[i];
+  }
+  if (PAY) {
+    uint32_t pay[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) pay[j] = row_idx(j) < cnt ? a.in_pay[cb + row_idx(j)] : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (row_idx(j) < cnt) s_stage[lpos[j]] = pay[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int i = k * NT + tid;
+      if (i < cnt) a.Q[gpos_of(k, i)] = s_stage[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <int WAVES, int ITEMS, int RBITS>
+static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st) {
+  const int64_t tile = (int64_t)WAVES * kWave * ITEMS;
+  const unsigned grid = (unsigned)((a.m + tile - 1) / tile);
+  const dim3 blk(WAVES * kWave);
+#define GT_L(C, P, L) hipLaunchKernelGGL((k_lsd<WAVES, ITEMS, RBITS, C, P, L>), dim3(grid), blk, 0, st, a)
+  if (csr_in) {
+    if (pay) { if (last) GT_L(true, true, true); else GT_L(true, true, false); }
+    else { if (last) GT_L(true, false, true); else GT_L(true, false, false); }
+  } else {
+    if (pay) { if (last) GT_L(false, true, true); else GT_L(false, true, false); }
+    else { if (last) GT_L(false, false, true); else GT_L(false, false, false); }
+  }
+#undef GT_L
+  return hipGetLastError();
+}
+
+int64_t lsd_tile_size(int variant) {
+  switch (variant) {
+    case 2: return 16 * kWave * 8;
+    case 3: return 8 * kWave * 8;
+    default: return 8 * kWave * 16;
+  }
+}
+
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last,
+                      hipStream_t st) {
+  if (a.m <= 0) return hipSuccess;
+  const int rb = rbits <= 8 ? 8 : (rbits <= 9 ? 9 : 10);
+#define GT_V(W, I)                                                                       \
+  return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, st)                      \
+                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, st)           \
+                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, st))
+  switch (variant) {
+    case 2:  // 16 waves: the 10-bit lane-mask tables would not fit LDS; same tile as variant 1
+      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, st);
+      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, st) : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, st);
+    case 3: GT_V(8, 8);
+    default: GT_V(8, 16);
+  }
+#undef GT_V
+}
+
+int64_t final_tile_size() { return 8 * kWave * 16; }
+
+hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_items, dim3((unsigned)((a.nbins + 255) / 256)), dim3(256), 0, st, a.bin_start, a.nbins,
+                     final_tile_size(), a.nch, a.T, a.n, a.m);
+  return hipGetLastError();
+}
+
+hipError_t launch_item_map(const FinalArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_item_map, dim3((unsigned)((a.nbins + 255) / 256)), dim3(256), 0, st, a.nch, a.item_base,
+                     a.nbins, a.item_bin, a.bigbins, a.nbig);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st) {
+  if (max_big <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_big_scan<256>), dim3((unsigned)max_big), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int64_t scan_tile_size() { return 256 * 16; }
+
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint64_t *status, uint32_t *ticket,
+                           uint32_t *total, hipStream_t st) {
+  const int64_t tiles = (len + scan_tile_size() - 1) / scan_tile_size();
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scan_u32<256, 16>), dim3((unsigned)tiles), dim3(256), 0, st, in, out, len, status, ticket,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_count(const FinalArgs &a, int64_t max_items, hipStream_t st) {
+  if (max_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_big_count<8, 16, kMaxFineBits>), dim3((unsigned)max_items), dim3(8 * kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(const FinalArgs &a, int64_t max_items, bool pay, hipStream_t st) {
+  if (max_items <= 0) return hipSuccess;
+  const dim3 grid((unsigned)max_items), blk(8 * kWave);
+  if (pay) hipLaunchKernelGGL((k_final<8, 16, kMaxFineBits, true>), grid, blk, 0, st, a);
+  else hipLaunchKernelGGL((k_final<8, 16, kMaxFineBits, false>), grid, blk, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)blocks), dim3(256), 0, st, O, n, m, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile, int64_t ntiles, int32_t *out,
+                           hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_src, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st, O, n, m, tile, ntiles,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int nblocks, uint32_t *part,
+                       uint32_t *err, hipStream_t st) {
+  switch (h.passes) {
+    case 1: hipLaunchKernelGGL(k_hist<1>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
+    case 2: hipLaunchKernelGGL(k_hist<2>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
+    default: hipLaunchKernelGGL(k_hist<3>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *digit_start,
+                             uint64_t *bin_start, int64_t nbins_total, int64_t m, hipStream_t st) {
+  hipLaunchKernelGGL(k_digit_scan, dim3(h.passes), dim3(1024), 0, st, part, nblocks, h, digit_start, bin_start,
+                     nbins_total, m);
+  return hipGetLastError();
+}
+
+}  // namespace gt

@@ -1,0 +1,77 @@
+// Plan structures shared by the C ABI, the parameter policies and the
+// batched launcher.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/gt.h"
+
+namespace gt {
+
+struct GraphPlan {
+  int64_t n, m;
+  bool pay;
+  // chosen parameters
+  int fine_bits;   // log2 of the destination range of one k_final workgroup
+  int digit_bits;  // maximum digit width per partition pass
+  int variant;     // tile variant of k_lsd
+  // derived
+  int passes, bits[3], shift[3], max_bits, total_bits;
+  int64_t nbins_total, nbins, tile, ntiles;
+  // workspace byte offsets (relative to the workspace start)
+  size_t off_err, off_ticket, off_part, off_digit, off_bin, off_status, off_tsrc;
+  size_t off_a_src, off_a_key, off_a_pay, off_a2_src, off_a2_key, off_a2_pay;
+  size_t off_b_src, off_b_key, off_b_pay;
+  size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big;
+  int64_t max_big;
+  int64_t max_items;
+  size_t ws_end;
+  // sampled features (when the policy sampled the graph)
+  float features[32];
+  int nfeatures;
+};
+
+}  // namespace gt
+
+namespace gt {
+// Per-launch HIP events recorded on the launch stream while profiling is on.
+struct ProfRec {
+  const char *name;
+  hipEvent_t start, stop;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;   // recorded since the last read
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get();
+  hipError_t begin(const char *name, hipStream_t st);
+  hipError_t end(hipStream_t st);
+};
+}  // namespace gt
+
+struct gt_plan_st {
+  int32_t count;
+  bool validate;
+  std::vector<gt::GraphPlan> graphs;
+  size_t ws_bytes;
+  gt::Profiler prof;
+  ~gt_plan_st();
+};
+
+namespace gt {
+
+void finalize_params(GraphPlan &p, size_t base);
+size_t graph_workspace_bound(int64_t n, int64_t m, bool pay);
+size_t plan_scratch_bytes(const gt_csr_t *graphs, int32_t count);
+gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count, const gt_options_t &opt,
+                        void *workspace, size_t workspace_bytes, hipStream_t st);
+gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
+                        bool reset_status, Profiler *prof, hipStream_t st);
+gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
+                          hipStream_t st);
+
+}  // namespace gt

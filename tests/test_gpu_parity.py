@@ -1,0 +1,187 @@
+"""GPU parity: the HIP transposition against the CPU oracle, bit for bit.
+
+Inputs are seeded and synthetic.  Every case prints its name before it runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(O, D, P, dev):
+    O_t = torch.from_numpy(np.ascontiguousarray(O)).to(dev)
+    D_t = torch.from_numpy(np.ascontiguousarray(D)).to(dev)
+    P_t = torch.from_numpy(np.ascontiguousarray(P).view(np.int32)).to(dev) if P is not None else None
+    return O_t, D_t, P_t
+
+
+def gpu_transpose(O, D, P, dev, **opt):
+    import paper_2501_06872_amd as gt
+    O_t, D_t, P_t = to_dev(O, D, P, dev)
+    options = gt.make_options(**opt) if opt else None
+    plan = gt.Plan([(O_t, D_t, P_t)], options)
+    T, S, Q = plan.run(O_t, D_t, P_t)
+    torch.cuda.synchronize()
+    st = plan.device_status()
+    return (T.cpu().numpy(), S.cpu().numpy(), Q.cpu().numpy().view(np.uint32) if Q is not None else None,
+            st, plan.params())
+
+
+def assert_parity(O, D, P, dev, label, **opt):
+    say(f"[case] {label} n={len(O) - 1} m={len(D)} payload={P is not None} opt={opt}")
+    T, S, Q, st, params = gpu_transpose(O, D, P, dev, **opt)
+    assert st == 0, f"device status {st}"
+    rT, rS, rQ = oracle.transpose(O, D, P)
+    assert np.array_equal(T, rT), f"{label}: offsets differ"
+    assert np.array_equal(S, rS), f"{label}: sources differ at {np.flatnonzero(S != rS)[:5]}"
+    if P is not None:
+        assert np.array_equal(Q, rQ), f"{label}: payload differs"
+    return params
+
+
+def random_csr(rng, n, avg_deg, skew=None, sorted_lists=True, payload=False):
+    deg = rng.poisson(avg_deg, size=n)
+    O = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    m = int(O[-1])
+    if skew:
+        D = (rng.zipf(skew, size=m) - 1) % max(n, 1)
+    else:
+        D = rng.integers(0, max(n, 1), size=m)
+    D = D.astype(np.int32)
+    if sorted_lists:
+        for u in range(n):
+            D[O[u]:O[u + 1]].sort()
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
+    return O, D, P
+
+
+def test_rmat16_default(hip_device):
+    O, D, P = gen.workload("rmat16")
+    params = assert_parity(O, D, P, hip_device, "rmat16 (R-MAT scale 16, ef 16, seed 1)")
+    say("params", params)
+
+
+@pytest.mark.parametrize("payload", [False, True])
+def test_rmat_permuted_small(hip_device, payload):
+    O, D, P = gen.rmat(18, 16, seed=2, permute=True, payload=payload)
+    assert_parity(O, D, P, hip_device, "rmat18 permuted")
+
+
+def test_empty_and_degenerate(hip_device):
+    e32 = np.array([], dtype=np.int32)
+    assert_parity(np.array([0]), e32, None, hip_device, "n=0")
+    assert_parity(np.array([0, 0]), e32, None, hip_device, "n=1 m=0")
+    assert_parity(np.zeros(1001, dtype=np.int64), e32, None, hip_device, "n=1000 m=0")
+    assert_parity(np.array([0, 5]), np.zeros(5, dtype=np.int32), np.arange(5, dtype=np.uint32), hip_device,
+                  "n=1 five self-loops")
+    assert_parity(np.array([0, 1, 1]), np.array([1], dtype=np.int32), None, hip_device, "n=2 one edge")
+
+
+def test_star_into_one_vertex(hip_device):
+    # every vertex points at vertex 7 (in-degree = m: the multi-tile bin path)
+    n = 50000
+    O = np.arange(0, 3 * n + 1, 3, dtype=np.int64)
+    D = np.full(3 * n, 7, dtype=np.int32)
+    P = np.arange(3 * n, dtype=np.uint32)
+    assert_parity(O, D, P, hip_device, "star into vertex 7")
+
+
+def test_self_loops_and_cycle(hip_device):
+    n = 70001
+    O = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    D = np.repeat(np.arange(n), 2).astype(np.int32)
+    assert_parity(O, D, None, hip_device, "all self-loops")
+    O = np.arange(n + 1, dtype=np.int64)
+    D = ((np.arange(n) + 1) % n).astype(np.int32)
+    assert_parity(O, D, None, hip_device, "directed cycle")
+
+
+def test_unsorted_lists_duplicates_payload_bits(hip_device):
+    rng = np.random.default_rng(21)
+    O, D, P = random_csr(rng, 20000, 9, skew=1.3, sorted_lists=False, payload=True)
+    special = np.array([0x7FC00001, 0x80000000, 0x00000001, 0x7F800000, 0xFF800000], dtype=np.uint32)
+    P[: special.size * 50] = np.tile(special, 50)
+    assert_parity(O, D, P, hip_device, "unsorted lists, duplicates, NaN/-0/denormal payload")
+
+
+def test_one_source_spanning_many_tiles(hip_device):
+    # vertex 3 has 100k out-edges: its list crosses several 8K tiles; many empty rows
+    n = 300000
+    deg = np.zeros(n, dtype=np.int64)
+    deg[3] = 100000
+    deg[n - 1] = 17
+    deg[1000:1100] = 5
+    O = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    rng = np.random.default_rng(3)
+    D = np.sort(rng.integers(0, n, size=int(O[-1]))).astype(np.int32)
+    D[: 40000] = 12345  # a duplicate run crossing tile boundaries
+    D[:100000].sort()
+    assert_parity(O, D, None, hip_device, "one source spanning tiles")
+
+
+@pytest.mark.parametrize("n,avg,skew,payload", [
+    (3, 2, None, False), (1000, 5, 1.5, True), (4097, 16, None, False), (65539, 16, 1.2, True),
+    (300001, 7, 1.4, False), (1 << 20, 3, None, True),
+])
+def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
+    rng = np.random.default_rng(n)
+    O, D, P = random_csr(rng, n, avg, skew=skew, payload=payload)
+    assert_parity(O, D, P, hip_device, f"random n={n} avg={avg} skew={skew}")
+
+
+@pytest.mark.parametrize("fine_bits,digit_bits,variant", [
+    (1, 4, 1), (4, 6, 3), (8, 10, 2), (9, 4, 1), (5, 10, 3), (7, 8, 2), (9, 10, 1), (6, 5, 1),
+])
+def test_parameter_sweep_same_output(hip_device, fine_bits, digit_bits, variant):
+    # 1, 2 and 3 partition passes, every tile variant, narrow and wide bins
+    O, D, P = gen.rmat(17, 8, seed=9, permute=True, payload=True)
+    params = assert_parity(O, D, P, hip_device, "rmat17p sweep", policy=1, fine_bits=fine_bits,
+                           digit_bits=digit_bits, variant=variant)
+    say("params", params)
+
+
+def test_determinism_repeated_runs(hip_device):
+    import paper_2501_06872_amd as gt
+    O, D, P = gen.rmat(19, 16, seed=4, permute=True, payload=True)
+    say(f"[case] determinism rmat19p m={len(D)}")
+    O_t, D_t, P_t = to_dev(O, D, P, hip_device)
+    plan = gt.Plan([(O_t, D_t, P_t)])
+    outs = []
+    for _ in range(3):
+        T, S, Q = plan.run(O_t, D_t, P_t)
+        torch.cuda.synchronize()
+        outs.append((T.clone(), S.clone(), Q.clone()))
+    for T, S, Q in outs[1:]:
+        assert torch.equal(T, outs[0][0]) and torch.equal(S, outs[0][1]) and torch.equal(Q, outs[0][2])
+
+
+def test_invalid_graph_reported(hip_device):
+    # indices outside [0, n) are reported through the device status word
+    import paper_2501_06872_amd as gt
+    n = 5000
+    O = np.arange(0, 4 * n + 1, 4, dtype=np.int64)
+    rng = np.random.default_rng(1)
+    D = rng.integers(0, n, size=4 * n).astype(np.int32)
+    D[123] = n          # one past the end
+    D[4567] = -1
+    say("[case] invalid indices")
+    _, _, _, st, _ = gpu_transpose(O, D, None, hip_device)
+    assert st == gt.GT_ERR_INVALID_GRAPH
+    # bad offsets with validation on
+    O2 = O.copy()
+    O2[10] = O2[11] + 1
+    D2 = rng.integers(0, n, size=4 * n).astype(np.int32)
+    say("[case] invalid offsets, validate=1")
+    _, _, _, st, _ = gpu_transpose(O2, D2, None, hip_device, validate=True)
+    assert st == gt.GT_ERR_INVALID_GRAPH
