@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--check", action="store_true", help="check the output on sampled vertex ranges")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="copy 1 GiB once before timing (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path is a single-GPU kernel pipeline); got --gpus {args.gpus}",
@@ -130,6 +132,13 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] params {params}; warmup done", file=sys.stderr, flush=True)
 
+    if args.calibrate:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE scale the counters
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     plan.profile(True)
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

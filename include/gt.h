@@ -86,7 +86,12 @@ typedef struct {
   int32_t validate;      /* 1: check offsets/indices on the device (status word) */
   uint64_t seed;         /* seed of the degree-sampling pass */
   const char *model_path;/* weights of the learned policy (GT_POLICY_MLP) */
+  int32_t flags;         /* GT_FLAG_* */
 } gt_options_t;
+
+/* Flags.  GT_FLAG_WIDE_STATUS forces the 64-bit look-back words that graphs
+ * with m >= 2^31 use, so that path can be tested on small graphs. */
+enum { GT_FLAG_WIDE_STATUS = 1 };
 
 typedef struct gt_plan_st *gt_plan_t;
 

@@ -46,7 +46,7 @@ class CSC(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("fine_bits", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("validate", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("model_path", ctypes.c_char_p)]
+                ("model_path", ctypes.c_char_p), ("flags", ctypes.c_int32)]
 
 
 _lib = None
@@ -110,10 +110,13 @@ def _check_inputs(offsets, indices, payload):
             raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
 
 
+FLAG_WIDE_STATUS = 1
+
+
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
-                 model_path=None):
+                 model_path=None, flags=0):
     return Options(policy, fine_bits, digit_bits, variant, int(bool(validate)), seed,
-                   model_path.encode() if model_path else None)
+                   model_path.encode() if model_path else None, flags)
 
 
 class Plan:

@@ -75,8 +75,10 @@ void finalize_params(GraphPlan &p, size_t base) {
   p.off_ticket = take(sizeof(uint32_t) * kMaxPasses);
   p.off_part = take(sizeof(uint32_t) * (size_t)kHistBlocks * kMaxPasses * kMaxRadix);
   p.off_digit = take(sizeof(uint64_t) * kMaxPasses * (kMaxRadix + 1));
+  p.off_dtot = take(sizeof(uint64_t) * kMaxPasses * kMaxRadix);
   p.off_bin = take(sizeof(uint64_t) * (size_t)(p.nbins_total + 1));
-  p.off_status = take(sizeof(uint64_t) * (size_t)p.ntiles * ((size_t)1 << p.max_bits));
+  p.wide_status = p.force_wide || p.m >= (int64_t(1) << 31);
+  p.off_status = take((p.wide_status ? 8 : 4) * (size_t)p.ntiles * ((size_t)1 << p.max_bits));
   p.off_tsrc = take(sizeof(int32_t) * (size_t)std::max<int64_t>(p.ntiles, 1));
   const size_t m = (size_t)p.m;
   p.off_a_src = p.off_a_key = p.off_a_pay = 0;
@@ -111,10 +113,11 @@ void finalize_params(GraphPlan &p, size_t base) {
 size_t graph_workspace_bound(int64_t n, int64_t m, bool pay) {
   size_t best = 0;
   for (int fb = 0; fb <= kMaxFineBits; ++fb)
-    for (int variant = 1; variant <= 3; ++variant)
+    for (int variant = 1; variant <= 4; ++variant)
       for (int db = 4; db <= 10; ++db) {
         GraphPlan p{};
         p.n = n; p.m = m; p.pay = pay; p.fine_bits = fb; p.digit_bits = db; p.variant = variant;
+        p.force_wide = true;
         finalize_params(p, 0);
         best = std::max(best, p.ws_end);
       }
@@ -163,22 +166,23 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
   uint64_t *digit = reinterpret_cast<uint64_t *>(ws + p.off_digit);
   uint64_t *bins = reinterpret_cast<uint64_t *>(ws + p.off_bin);
-  uint64_t *status = reinterpret_cast<uint64_t *>(ws + p.off_status);
+  void *status = ws + p.off_status;
   int32_t *tsrc = reinterpret_cast<int32_t *>(ws + p.off_tsrc);
 
   HistArgs h{};
   h.passes = p.passes;
   for (int i = 0; i < p.passes; ++i) { h.shift[i] = p.shift[i]; h.bits[i] = p.bits[i]; }
   GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, kHistBlocks, part, err, st));
-  GT_TIMED("k_digit_scan", launch_digit_scan(part, kHistBlocks, h, digit, bins, p.nbins_total, p.m, st));
+  GT_TIMED("k_digit_scan", launch_digit_scan(part, kHistBlocks, h, reinterpret_cast<uint64_t *>(ws + p.off_dtot),
+                                             digit, bins, p.nbins_total, p.m, st));
   GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
 
-  const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * 2;
+  const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
   const int32_t *cur_src = nullptr;
   const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
   for (int pass = 0; pass < p.passes; ++pass) {
     const bool first = pass == 0, last = pass == p.passes - 1;
-    GT_TIMED("k_fill_status", launch_fill(reinterpret_cast<uint32_t *>(status), status_words, 0u, st));
+    GT_TIMED("k_fill_status", launch_fill(static_cast<uint32_t *>(status), status_words, 0u, st));
     GT_CHK(launch_fill(ticket + pass, 1, 0u, st));
     LsdArgs a{};
     a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc;
@@ -204,7 +208,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
     a.fine_mask = (1u << p.fine_bits) - 1u;
     a.bin_start = bins;
     static const char *kLsdNames[kMaxPasses] = {"k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2"};
-    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, st));
+    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, p.wide_status, st));
     cur_src = a.out_src;
     cur_key = a.out_key32;
     cur_pay = a.out_pay;
@@ -223,10 +227,10 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
   f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
   f.nbig = f.total_items + 2;
-  uint64_t *sstatus = reinterpret_cast<uint64_t *>(ws + p.off_sstatus);
+  uint32_t *sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
   const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
   GT_TIMED("k_bin_items", launch_bin_items(f, st));
-  GT_CHK(launch_fill(reinterpret_cast<uint32_t *>(sstatus), 2 * (uint64_t)scan_tiles, 0u, st));
+  GT_CHK(launch_fill(sstatus, (uint64_t)scan_tiles, 0u, st));
   GT_CHK(launch_fill(f.total_items + 1, 2, 0u, st));  // scan ticket, big-bin count
   GT_TIMED("k_scan_u32", launch_scan_u32(f.nch, f.item_base, p.nbins, sstatus, f.total_items + 1, f.total_items, st));
   GT_TIMED("k_item_map", launch_item_map(f, st));
@@ -281,7 +285,7 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_TABLE) return GT_ERR_INVALID_ARGUMENT;
   if (o.policy == GT_POLICY_FIXED) {
     if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
-        (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 3)
+        (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 4)
       return GT_ERR_UNSUPPORTED;
   }
   gt_plan_st *plan = new (std::nothrow) gt_plan_st();

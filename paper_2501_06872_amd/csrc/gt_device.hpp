@@ -107,55 +107,89 @@ __device__ T block_excl_scan(T *s, int len, T *wsum) {
   return total;
 }
 
-// Status word of the decoupled look-back (Merrill & Garland 2016):
-// bits 63..62 flag (0 = not yet published, 1 = tile aggregate, 2 = inclusive
-// prefix), bits 61..0 the count.
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// Status words of the decoupled look-back (Merrill & Garland 2016), one per
+// (tile, column): not yet published, the tile's own aggregate, or the
+// inclusive prefix through the tile.
+//  64-bit: bits 63..62 flag (0 none, 1 aggregate, 2 inclusive), 61..0 count.
+//  32-bit (totals below 2^31): 0 none; aggregate a stored as a + 1 (bit 31
+//          clear); inclusive p stored as 2^31 | p.
+template <typename W> struct Status;
+template <> struct Status<uint64_t> {
+  static __device__ __forceinline__ uint64_t agg(uint64_t a) { return (1ull << 62) | a; }
+  static __device__ __forceinline__ uint64_t incl(uint64_t p) { return (2ull << 62) | p; }
+  static __device__ __forceinline__ bool ready(uint64_t s) { return (s >> 62) != 0; }
+  static __device__ __forceinline__ bool is_incl(uint64_t s) { return (s >> 62) == 2; }
+  static __device__ __forceinline__ uint64_t value(uint64_t s) { return s & ((1ull << 62) - 1); }
+};
+template <> struct Status<uint32_t> {
+  static __device__ __forceinline__ uint32_t agg(uint64_t a) { return (uint32_t)a + 1u; }
+  static __device__ __forceinline__ uint32_t incl(uint64_t p) { return 0x80000000u | (uint32_t)p; }
+  static __device__ __forceinline__ bool ready(uint32_t s) { return s != 0u; }
+  static __device__ __forceinline__ bool is_incl(uint32_t s) { return (s >> 31) != 0u; }
+  static __device__ __forceinline__ uint64_t value(uint32_t s) { return (s >> 31) ? (s & 0x7FFFFFFFu) : s - 1u; }
+};
 
-__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
+template <typename W>
+__device__ __forceinline__ W status_load(const W *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+template <typename W>
+__device__ __forceinline__ void status_store(W *p, W v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Exclusive prefix of this tile's `count` over all earlier tiles of the same
-// column (`stride` = number of columns); publishes aggregate, then inclusive.
-// Predecessors are read in windows of kLookWin independent loads, so one
-// round trip covers several tiles of the chain.
+// column (`stride` = number of columns); publishes the aggregate, then the
+// inclusive prefix.  The immediate predecessor is read first (usually it is
+// already inclusive); a longer chain is then read kLookWin tiles per round
+// trip.
 constexpr int kLookWin = 8;
-__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *status, int64_t tile, int64_t stride,
-                                                      int64_t col, uint64_t count) {
-  uint64_t *mine = status + tile * stride + col;
+template <typename W>
+__device__ __forceinline__ uint64_t lookback_exclusive(W *status, int64_t tile, int64_t stride, int64_t col,
+                                                      uint64_t count) {
+  using S = Status<W>;
+  W *mine = status + tile * stride + col;
   if (tile == 0) {
-    status_store(mine, kFlagIncl | count);
+    status_store(mine, S::incl(count));
     return 0;
   }
-  status_store(mine, kFlagAgg | count);
+  status_store(mine, S::agg(count));
   uint64_t excl = 0;
   int64_t t = tile - 1;
+  {
+    const W *p = status + t * stride + col;
+    W s = status_load(p);
+    while (!S::ready(s)) {
+      __builtin_amdgcn_s_sleep(1);
+      s = status_load(p);
+    }
+    excl = S::value(s);
+    if (S::is_incl(s)) {
+      status_store(mine, S::incl(excl + count));
+      return excl;
+    }
+    --t;
+  }
   bool done = false;
   while (!done) {
-    uint64_t s[kLookWin];
+    W s[kLookWin];
 #pragma unroll
-    for (int k = 0; k < kLookWin; ++k) s[k] = (t - k >= 0) ? status_load(status + (t - k) * stride + col) : kFlagIncl;
+    for (int k = 0; k < kLookWin; ++k) s[k] = (t - k >= 0) ? status_load(status + (t - k) * stride + col) : S::incl(0);
 #pragma unroll
     for (int k = 0; k < kLookWin; ++k) {
       if (!done) {
-        const uint64_t *p = status + (t - k) * stride + col;
-        while ((s[k] >> 62) == 0) {
+        const W *p = status + (t - k) * stride + col;
+        while (!S::ready(s[k])) {
           __builtin_amdgcn_s_sleep(1);
           s[k] = status_load(p);
         }
-        excl += s[k] & kValueMask;
-        if ((s[k] >> 62) == 2) done = true;
+        excl += S::value(s[k]);
+        if (S::is_incl(s[k])) done = true;
       }
     }
     t -= kLookWin;
   }
-  status_store(mine, kFlagIncl | (excl + count));
+  status_store(mine, S::incl(excl + count));
   return excl;
 }
 

@@ -8,7 +8,7 @@ namespace gt {
 constexpr int kMaxPasses = 3;
 constexpr int kMaxRadix = 1024;   // digit width <= 10 bits
 constexpr int kMaxFineBits = 9;   // bins of <= 512 destinations in k_final
-constexpr int kHistBlocks = 512;
+constexpr int kHistBlocks = 1280;
 
 constexpr uint32_t kErrBadIndex = 1u;
 constexpr uint32_t kErrBadOffsets = 2u;
@@ -37,7 +37,7 @@ struct LsdArgs {
   // digit of this pass: (key >> shift) & ((1 << bits) - 1)
   int shift, bits;
   const uint64_t *digit_start;
-  uint64_t *status;
+  void *status;        // uint32_t words when m < 2^31, else uint64_t
   uint32_t *ticket;
   int64_t m, n;
   // last pass: bin bookkeeping
@@ -68,12 +68,13 @@ struct FinalArgs {
 };
 
 int64_t lsd_tile_size(int variant);
-hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st);
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide_status,
+                      hipStream_t st);
 int64_t final_tile_size();
 int64_t scan_tile_size();
 hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st);
 hipError_t launch_item_map(const FinalArgs &a, hipStream_t st);
-hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint64_t *status, uint32_t *ticket,
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint32_t *status, uint32_t *ticket,
                            uint32_t *total, hipStream_t st);
 hipError_t launch_big_count(const FinalArgs &a, int64_t max_items, hipStream_t st);
 hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st);
@@ -84,7 +85,8 @@ hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile,
                            hipStream_t st);
 hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int nblocks, uint32_t *part,
                        uint32_t *err, hipStream_t st);
-hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *digit_start,
-                             uint64_t *bin_start, int64_t nbins_total, int64_t m, hipStream_t st);
+hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
+                             uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
+                             hipStream_t st);
 
 }  // namespace gt

@@ -88,13 +88,35 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) atomicAdd(&hw[p * kMaxRadix + ((u >> sh[p]) & mk[p])], 1u);
   };
+  // Four consecutive destinations per lane.  Runs of equal digits (common
+  // when destinations are close to their sources) are added once: per lane
+  // when its four digits agree, per wave when every lane's do.
+  auto count4 = [&](uint4 q) {
+    bad |= (q.x >= un) | (q.y >= un) | (q.z >= un) | (q.w >= un);
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const uint32_t dx = (q.x >> sh[p]) & mk[p], dy = (q.y >> sh[p]) & mk[p];
+      const uint32_t dz = (q.z >> sh[p]) & mk[p], dw = (q.w >> sh[p]) & mk[p];
+      const bool same4 = (dx == dy) & (dy == dz) & (dz == dw);
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(dx);
+      const uint64_t active = __ballot(1);
+      if (__all(same4 && dx == d0)) {
+        if ((uint64_t)1 << (threadIdx.x & 63) == (active & -active))
+          atomicAdd(&hw[p * kMaxRadix + d0], 4u * (uint32_t)__popcll(active));
+      } else if (same4) {
+        atomicAdd(&hw[p * kMaxRadix + dx], 4u);
+      } else {
+        atomicAdd(&hw[p * kMaxRadix + dx], 1u);
+        atomicAdd(&hw[p * kMaxRadix + dy], 1u);
+        atomicAdd(&hw[p * kMaxRadix + dz], 1u);
+        atomicAdd(&hw[p * kMaxRadix + dw], 1u);
+      }
+    }
+  };
   const int64_t nvec = m >> 2;
   const uint4 *D4 = reinterpret_cast<const uint4 *>(D);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid; i < nvec; i += stride) {
-    const uint4 q = D4[i];
-    count(q.x); count(q.y); count(q.z); count(q.w);
-  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid; i < nvec; i += stride) count4(D4[i]);
   for (int64_t i = (nvec << 2) + blockIdx.x * (int64_t)blockDim.x + tid; i < m; i += stride) count((uint32_t)D[i]);
   if (bad) atomicOr(err, kErrBadIndex);
   __syncthreads();
@@ -107,21 +129,34 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int
   }
 }
 
-// Step 2 (digit level): sum the partial histograms, exclusive scan per pass.
-// One workgroup per pass.  Also initialises the look-back tickets and the
-// terminal bin start.
-__global__ __launch_bounds__(1024) void k_digit_scan(const uint32_t *__restrict__ part, int nblocks, HistArgs h,
+// Step 2 (digit level), part 1: sum the per-workgroup partial histograms.
+// Block (pass, 64-digit group); four thread groups split the partials.
+__global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict__ part, int nblocks, HistArgs h,
+                                                      uint64_t *totals) {
+  __shared__ uint64_t s_sum[4][64];
+  const int p = blockIdx.x / (kMaxRadix / 64), g = blockIdx.x % (kMaxRadix / 64);
+  const int tid = threadIdx.x, d = g * 64 + (tid & 63), q = tid >> 6;
+  if (p >= h.passes) return;
+  const int radix = 1 << h.bits[p];
+  uint64_t s = 0;
+  if (d < radix)
+    for (int b = q; b < nblocks; b += 4) s += part[(int64_t)b * kMaxPasses * kMaxRadix + p * kMaxRadix + d];
+  s_sum[q][tid & 63] = s;
+  __syncthreads();
+  if (q == 0 && d < radix) totals[p * kMaxRadix + d] = s_sum[0][tid] + s_sum[1][tid] + s_sum[2][tid] + s_sum[3][tid];
+}
+
+// Step 2 (digit level), part 2: exclusive scan of the digit totals of every
+// pass -> start of each digit in the partitioned stream.  Also the terminal
+// bin start.
+__global__ __launch_bounds__(1024) void k_digit_scan(const uint64_t *__restrict__ totals, HistArgs h,
                                                      uint64_t *digit_start, uint64_t *bin_start,
                                                      int64_t nbins_total, int64_t m) {
   __shared__ uint64_t s_tot[kMaxRadix];
   __shared__ uint64_t s_wsum[1024 / kWave + 1];
   const int p = blockIdx.x, tid = threadIdx.x;
   const int radix = 1 << h.bits[p];
-  for (int d = tid; d < radix; d += blockDim.x) {
-    uint64_t s = 0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * kMaxPasses * kMaxRadix + p * kMaxRadix + d];
-    s_tot[d] = s;
-  }
+  for (int d = tid; d < radix; d += blockDim.x) s_tot[d] = totals[p * kMaxRadix + d];
   __syncthreads();
   block_excl_scan<1024, uint64_t>(s_tot, radix, s_wsum);
   for (int d = tid; d < radix; d += blockDim.x) digit_start[p * (kMaxRadix + 1) + d] = s_tot[d];
@@ -132,7 +167,7 @@ __global__ __launch_bounds__(1024) void k_digit_scan(const uint32_t *__restrict_
 // ---------------------------------------------------------------------------
 // k_lsd: one stable partition pass by a destination digit.
 // ---------------------------------------------------------------------------
-template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST>
+template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST, typename SW>
 __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   constexpr int NT = WAVES * kWave;
   constexpr int TILE = NT * ITEMS;
@@ -195,7 +230,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   __syncthreads();
   // look-back per digit across tiles
   for (int d = tid; d < radix; d += NT) {
-    const uint64_t excl = lookback_exclusive(a.status, tile, radix, d, s_tot[d]);
+    const uint64_t excl = lookback_exclusive<SW>(static_cast<SW *>(a.status), tile, radix, d, s_tot[d]);
     s_gbase[d] = a.digit_start[d] + excl;
   }
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets
@@ -330,7 +365,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
 // ---------------------------------------------------------------------------
 template <int NT, int ITEMS>
 __global__ __launch_bounds__(NT) void k_scan_u32(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                                 int64_t len, uint64_t *status, uint32_t *ticket, uint32_t *total) {
+                                                 int64_t len, uint32_t *status, uint32_t *ticket, uint32_t *total) {
   constexpr int TILE = NT * ITEMS;
   __shared__ uint32_t s_w[NT / kWave + 1];
   __shared__ int64_t s_tile;
@@ -354,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_scan_u32(const uint32_t *__restrict__ in
     uint32_t run = 0;
     for (int i = 0; i < NT / kWave; ++i) { const uint32_t c = s_w[i]; s_w[i] = run; run += c; }
     s_w[NT / kWave] = run;
-    s_excl = lookback_exclusive(status, tile, 1, 0, run);
+    s_excl = lookback_exclusive<uint32_t>(status, tile, 1, 0, run);
     if ((tile + 1) * TILE >= len) *total = (uint32_t)(s_excl + run);
   }
   __syncthreads();
@@ -591,12 +626,12 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-template <int WAVES, int ITEMS, int RBITS>
-static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st) {
+template <int WAVES, int ITEMS, int RBITS, typename SW>
+static hipError_t launch_lsd_w(const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st) {
   const int64_t tile = (int64_t)WAVES * kWave * ITEMS;
   const unsigned grid = (unsigned)((a.m + tile - 1) / tile);
   const dim3 blk(WAVES * kWave);
-#define GT_L(C, P, L) hipLaunchKernelGGL((k_lsd<WAVES, ITEMS, RBITS, C, P, L>), dim3(grid), blk, 0, st, a)
+#define GT_L(C, P, L) hipLaunchKernelGGL((k_lsd<WAVES, ITEMS, RBITS, C, P, L, SW>), dim3(grid), blk, 0, st, a)
   if (csr_in) {
     if (pay) { if (last) GT_L(true, true, true); else GT_L(true, true, false); }
     else { if (last) GT_L(true, false, true); else GT_L(true, false, false); }
@@ -608,27 +643,39 @@ static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool las
   return hipGetLastError();
 }
 
+// status words: 32-bit when every prefix stays below 2^31, else 64-bit
+template <int WAVES, int ITEMS, int RBITS>
+static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide, hipStream_t st) {
+  return wide ? launch_lsd_w<WAVES, ITEMS, RBITS, uint64_t>(a, csr_in, pay, last, st)
+              : launch_lsd_w<WAVES, ITEMS, RBITS, uint32_t>(a, csr_in, pay, last, st);
+}
+
 int64_t lsd_tile_size(int variant) {
   switch (variant) {
     case 2: return 16 * kWave * 8;
     case 3: return 8 * kWave * 8;
+    case 4: return 16 * kWave * 16;
     default: return 8 * kWave * 16;
   }
 }
 
-hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last,
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide,
                       hipStream_t st) {
   if (a.m <= 0) return hipSuccess;
   const int rb = rbits <= 8 ? 8 : (rbits <= 9 ? 9 : 10);
 #define GT_V(W, I)                                                                       \
-  return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, st)                      \
-                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, st)           \
-                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, st))
+  return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, wide, st)                      \
+                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, wide, st)           \
+                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, wide, st))
   switch (variant) {
     case 2:  // 16 waves: the 10-bit lane-mask tables would not fit LDS; same tile as variant 1
-      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, st);
-      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, st) : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, st);
+      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, wide, st);
+      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, wide, st) : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, wide, st);
     case 3: GT_V(8, 8);
+    case 4:  // 16 waves x 16 edges: 16K-edge tiles (10-bit digits fall back to 8 waves x 32 edges? no: 8 x 16)
+      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, wide, st);
+      return rb == 8 ? launch_lsd_t<16, 16, 8>(a, csr_in, pay, last, wide, st)
+                     : launch_lsd_t<16, 16, 9>(a, csr_in, pay, last, wide, st);
     default: GT_V(8, 16);
   }
 #undef GT_V
@@ -656,7 +703,7 @@ hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st) 
 
 int64_t scan_tile_size() { return 256 * 16; }
 
-hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint64_t *status, uint32_t *ticket,
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint32_t *status, uint32_t *ticket,
                            uint32_t *total, hipStream_t st) {
   const int64_t tiles = (len + scan_tile_size() - 1) / scan_tile_size();
   if (tiles <= 0) return hipSuccess;
@@ -713,9 +760,11 @@ hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h
   return hipGetLastError();
 }
 
-hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *digit_start,
-                             uint64_t *bin_start, int64_t nbins_total, int64_t m, hipStream_t st) {
-  hipLaunchKernelGGL(k_digit_scan, dim3(h.passes), dim3(1024), 0, st, part, nblocks, h, digit_start, bin_start,
+hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
+                             uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_digit_reduce, dim3(h.passes * (kMaxRadix / 64)), dim3(256), 0, st, part, nblocks, h, totals);
+  hipLaunchKernelGGL(k_digit_scan, dim3(h.passes), dim3(1024), 0, st, totals, h, digit_start, bin_start,
                      nbins_total, m);
   return hipGetLastError();
 }

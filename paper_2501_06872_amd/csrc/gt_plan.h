@@ -21,8 +21,10 @@ struct GraphPlan {
   // derived
   int passes, bits[3], shift[3], max_bits, total_bits;
   int64_t nbins_total, nbins, tile, ntiles;
+  bool wide_status;  // 64-bit look-back words (m >= 2^31)
+  bool force_wide;
   // workspace byte offsets (relative to the workspace start)
-  size_t off_err, off_ticket, off_part, off_digit, off_bin, off_status, off_tsrc;
+  size_t off_err, off_ticket, off_part, off_digit, off_dtot, off_bin, off_status, off_tsrc;
   size_t off_a_src, off_a_key, off_a_pay, off_a2_src, off_a2_key, off_a2_pay;
   size_t off_b_src, off_b_key, off_b_pay;
   size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big;

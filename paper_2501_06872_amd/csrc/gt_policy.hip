@@ -34,6 +34,7 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
     p.m = graphs[i].m;
     p.pay = graphs[i].payload != nullptr;
     heuristic(p);
+    p.force_wide = (opt.flags & GT_FLAG_WIDE_STATUS) != 0;
     if (opt.policy == GT_POLICY_FIXED) {
       if (opt.fine_bits) p.fine_bits = opt.fine_bits;
       if (opt.digit_bits) p.digit_bits = opt.digit_bits;

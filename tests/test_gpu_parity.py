@@ -141,7 +141,7 @@ def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
 
 
 @pytest.mark.parametrize("fine_bits,digit_bits,variant", [
-    (1, 4, 1), (4, 6, 3), (8, 10, 2), (9, 4, 1), (5, 10, 3), (7, 8, 2), (9, 10, 1), (6, 5, 1),
+    (1, 4, 1), (4, 6, 3), (8, 10, 2), (9, 4, 1), (5, 10, 3), (7, 8, 2), (9, 10, 1), (6, 5, 1), (8, 9, 4), (3, 6, 4),
 ])
 def test_parameter_sweep_same_output(hip_device, fine_bits, digit_bits, variant):
     # 1, 2 and 3 partition passes, every tile variant, narrow and wide bins
@@ -149,6 +149,13 @@ def test_parameter_sweep_same_output(hip_device, fine_bits, digit_bits, variant)
     params = assert_parity(O, D, P, hip_device, "rmat17p sweep", policy=1, fine_bits=fine_bits,
                            digit_bits=digit_bits, variant=variant)
     say("params", params)
+
+
+@pytest.mark.parametrize("payload", [False, True])
+def test_wide_lookback_words(hip_device, payload):
+    # the 64-bit look-back words of graphs with m >= 2^31, forced on a small graph
+    O, D, P = gen.rmat(17, 8, seed=12, permute=True, payload=payload)
+    assert_parity(O, D, P, hip_device, "rmat17p wide status", flags=1)
 
 
 def test_determinism_repeated_runs(hip_device):
