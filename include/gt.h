@@ -136,6 +136,41 @@ gt_status gt_profile_read(gt_plan_t plan, int32_t max_kernels, char (*names)[32]
 
 const char *gt_status_string(gt_status s);
 
+/* ---- Degree sampling features (Section IV-C Step 0 sample of 1% of |V|
+ * edge positions; Section V-G coverage) of graph i of a plan built with the
+ * HEURISTIC or MLP policy: up to nmax floats; *nout = number available. */
+gt_status gt_plan_features(gt_plan_t plan, int32_t i, float *out, int32_t nmax, int32_t *nout);
+
+/* ---- Configuration grid of the learned and autotuned choices.  Every
+ * configuration yields the same output; they differ in speed only. */
+int32_t gt_num_configs(void);
+gt_status gt_config(int32_t idx, int32_t *fine_bits, int32_t *digit_bits, int32_t *variant);
+
+/* Autotuner: time every configuration on graph g (one warm-up, median of
+ * `reps` runs, HIP events on `stream`); ms_out has gt_num_configs() entries.
+ * Writes the transposition to `out`.  Synchronous. */
+gt_status gt_autotune(const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t workspace_bytes, void *stream,
+                      int32_t reps, float *ms_out);
+
+/* Use configuration `config` for graph i of a plan (e.g. the autotuner's
+ * best).  The required workspace never exceeds gt_workspace_size(). */
+gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config);
+
+/* ---- The learned parameter choice: MLP 16 -> 64 -> 64 -> 32 (ReLU, fp32),
+ * parameters W1[16][64] b1[64] W2[64][64] b2[64] W3[64][32] b3[32] in one
+ * device array.  Training primitives (device pointers, asynchronous):
+ *   forward:  y[batch][32] from x[batch][16]
+ *   gradient: y, loss = mean((y - target)^2), grad[nparams];
+ *             work holds gt_mlp_work_floats(batch) floats
+ *   adam:     one Adam step (step >= 1) on params with moments m1, m2 */
+int32_t gt_mlp_num_params(void);
+size_t gt_mlp_work_floats(int32_t batch);
+gt_status gt_mlp_forward(const float *params, const float *x, int32_t batch, float *y, void *stream);
+gt_status gt_mlp_gradient(const float *params, const float *x, const float *target, int32_t batch, float *y,
+                          float *grad, float *loss, float *work, void *stream);
+gt_status gt_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step, float lr, float beta1,
+                      float beta2, float eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,8 @@ baseline leg of ``bench.py`` may import this package; the library under
 * ``transpose_slice`` — the same restricted to a destination range, for checks
                         of full-size outputs on chosen vertex ranges.
 * ``transpose_py``    — the definition written out in pure Python (small cases).
-* ``mlp``             — fp64 forward/backward of the parameter-choice network.
+* ``features``        — the degree-sampling pass and feature vector (numpy).
+* ``mlp``             — fp64 forward/backward/Adam of the parameter-choice network.
 """
 import ctypes
 import os

@@ -25,7 +25,10 @@ POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP, POLICY_TABLE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan", "gt_transpose", "gt_transpose_batched", "gt_device_status",
-           "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_status_string")
+           "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
+           "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
+           "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
+NUM_FEATURES = 16
 
 
 class GTError(RuntimeError):
@@ -70,9 +73,21 @@ def lib():
         L.gt_plan_destroy.argtypes = [vp]
         L.gt_profile.argtypes = [vp, i32]
         L.gt_profile_read.argtypes = [vp, i32, vp, vp, vp, P(i32)]
+        L.gt_plan_features.argtypes = [vp, i32, vp, i32, P(i32)]
+        L.gt_config.argtypes = [i32, P(i32), P(i32), P(i32)]
+        L.gt_autotune.argtypes = [P(CSR), P(CSC), vp, sz, vp, i32, vp]
+        L.gt_plan_set_config.argtypes = [vp, i32, i32]
+        L.gt_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.gt_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        fl = ctypes.c_float
+        L.gt_mlp_adam.argtypes = [vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
+        L.gt_num_configs.argtypes = []
+        L.gt_mlp_num_params.argtypes = []
+        L.gt_mlp_work_floats.argtypes = [i32]
+        L.gt_mlp_work_floats.restype = ctypes.c_size_t
         L.gt_status_string.argtypes = [ctypes.c_int]
         L.gt_status_string.restype = ctypes.c_char_p
-        for f in EXPORTS[:-1]:
+        for f in EXPORTS[:-2]:
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -177,6 +192,15 @@ class Plan:
                                           self.workspace.numel(), _stream_ptr(self.device)), "gt_transpose_batched")
         return outs
 
+    def features(self, i=0):
+        out = (ctypes.c_float * 32)()
+        cnt = ctypes.c_int32()
+        _check(lib().gt_plan_features(self.handle, i, out, 32, ctypes.byref(cnt)), "gt_plan_features")
+        return [out[k] for k in range(min(cnt.value, 32))]
+
+    def set_config(self, i, config):
+        _check(lib().gt_plan_set_config(self.handle, i, config), "gt_plan_set_config")
+
     def profile(self, enable=True):
         _check(lib().gt_profile(self.handle, int(bool(enable))), "gt_profile")
 
@@ -210,3 +234,56 @@ def transpose(offsets, indices, payload=None, options=None):
     """Transpose one CSR graph on its GPU; returns (T, S, Q)."""
     plan = Plan([(offsets, indices, payload)], options)
     return plan.run(offsets, indices, payload)
+
+
+def num_configs():
+    return lib().gt_num_configs()
+
+
+def config(idx):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gt_config(idx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "gt_config")
+    return dict(fine_bits=a.value, digit_bits=b.value, variant=c.value)
+
+
+def autotune(offsets, indices, payload=None, reps=5, plan=None):
+    """Time every configuration (milliseconds, median of `reps`) on this graph."""
+    _check_inputs(offsets, indices, payload)
+    plan = plan if plan is not None else Plan([(offsets, indices, payload)], make_options(policy=POLICY_FIXED))
+    T, S, Q = plan.alloc_out(0, payload.dtype if payload is not None else None)
+    g = _csr(offsets, indices, payload)
+    o = CSC(T.data_ptr(), S.data_ptr() if S.numel() else None,
+            (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
+    ms = (ctypes.c_float * num_configs())()
+    _check(lib().gt_autotune(ctypes.byref(g), ctypes.byref(o), plan.workspace.data_ptr(), plan.workspace.numel(),
+                             _stream_ptr(plan.device), reps, ms), "gt_autotune")
+    return [ms[k] for k in range(num_configs())], (T, S, Q)
+
+
+# ---- training primitives of the parameter-choice MLP (torch float32 tensors on one GPU)
+def mlp_num_params():
+    return lib().gt_mlp_num_params()
+
+
+def mlp_forward(params, x):
+    y = torch.empty((x.shape[0], 32), dtype=torch.float32, device=x.device)
+    _check(lib().gt_mlp_forward(params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr(), _stream_ptr(x.device)),
+           "gt_mlp_forward")
+    return y
+
+
+def mlp_gradient(params, x, target, work=None):
+    B = x.shape[0]
+    y = torch.empty((B, 32), dtype=torch.float32, device=x.device)
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    if work is None:
+        work = torch.empty(lib().gt_mlp_work_floats(B), dtype=torch.float32, device=x.device)
+    _check(lib().gt_mlp_gradient(params.data_ptr(), x.data_ptr(), target.data_ptr(), B, y.data_ptr(), g.data_ptr(),
+                                 loss.data_ptr(), work.data_ptr(), _stream_ptr(x.device)), "gt_mlp_gradient")
+    return y, g, loss
+
+
+def mlp_adam(params, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().gt_mlp_adam(params.data_ptr(), grad.data_ptr(), m1.data_ptr(), m2.data_ptr(), step, lr, beta1,
+                             beta2, eps, _stream_ptr(params.device)), "gt_mlp_adam")

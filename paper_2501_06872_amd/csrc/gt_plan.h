@@ -34,6 +34,8 @@ struct GraphPlan {
   // sampled features (when the policy sampled the graph)
   float features[32];
   int nfeatures;
+  bool learned;  // parameters chosen by the MLP
+  int config;    // configuration index when chosen from the grid, else -1
 };
 
 }  // namespace gt

@@ -1,44 +1,166 @@
-// Parameter policies of a plan.
+// Parameter policies of a plan: heuristic (sizes + sampled features),
+// fixed, learned (MLP over sampled features), and the autotuner that times
+// every configuration.  None of them can change the output: every
+// configuration computes the same stable transposition.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "gt_internal.h"
+#include "gt_mlp.h"
 #include "gt_plan.h"
+#include "gt_sample.h"
 
 namespace gt {
 
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Sampling scratch of every graph of a plan, laid out back to back, then the
+// learned policy's parameters, inputs and outputs.
 size_t plan_scratch_bytes(const gt_csr_t *graphs, int32_t count) {
-  (void)graphs; (void)count;
-  return 0;
+  size_t total = 0;
+  for (int32_t i = 0; i < count; ++i) total += align256(sample_scratch_bytes(graphs[i].n, graphs[i].m));
+  total += align256(sizeof(float) * ((size_t)kMlpParams + (size_t)count * (kMlpIn + kMlpOut)));
+  return total;
 }
 
-// Size-only heuristic: a k_final bin should hold about one 8K-edge tile, so
-// fine_bits ~ log2(4096 / average in-degree); digits of up to 10 bits.
+// Heuristic: a k_final bin should hold about one 8K-edge tile, so
+// fine_bits ~ log2(8192 / average in-degree); digits of up to 10 bits; the
+// 8-wave x 16-edge tile.
 static void heuristic(GraphPlan &p) {
   const double avg = p.n > 0 ? (double)p.m / (double)p.n : 1.0;
-  int fb = (int)lround(log2(4096.0 / std::max(avg, 1.0)));
+  int fb = (int)lround(log2(8192.0 / std::max(avg, 1.0)));
   p.fine_bits = std::min(std::max(fb, 4), kMaxFineBits);
   p.digit_bits = 10;
   p.variant = 1;
 }
 
+// Scratch region at the end of the workspace.
+static char *scratch_base(const gt_csr_t *graphs, int32_t count, void *workspace, size_t workspace_bytes) {
+  const size_t need = plan_scratch_bytes(graphs, count);
+  if (workspace == nullptr || workspace_bytes < need + 256) return nullptr;
+  return static_cast<char *>(workspace) + ((workspace_bytes - need) & ~size_t(255));
+}
+
+// Sample every graph of the plan (one synchronisation for all of them) and
+// copy the feature vectors to the host.
+static gt_status sample_features(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count, uint64_t seed,
+                                 char *base, hipStream_t st) {
+  std::vector<float *> fdev(count);
+  size_t off = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (enqueue_sampling(graphs[i].offsets, graphs[i].indices, graphs[i].n, graphs[i].m,
+                         graphs[i].payload != nullptr, seed, base + off, &fdev[i], st) != hipSuccess)
+      return GT_ERR_HIP;
+    off += align256(sample_scratch_bytes(graphs[i].n, graphs[i].m));
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    GraphPlan &p = plan->graphs[i];
+    if (hipMemcpyAsync(p.features, fdev[i], sizeof(float) * kNumFeatures, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return GT_ERR_HIP;
+    p.nfeatures = kNumFeatures;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return GT_ERR_HIP;
+  return GT_OK;
+}
+
+// Model file: "GTMLP1\0\0", int32 inputs, hidden, outputs, nparams, then
+// float params[nparams], fmin[inputs], fmax[inputs] (the training range).
+struct MlpModel {
+  std::vector<float> params, fmin, fmax;
+};
+
+static bool load_model(const char *path, MlpModel &mdl) {
+  if (path == nullptr) return false;
+  FILE *f = fopen(path, "rb");
+  if (!f) return false;
+  char magic[8];
+  int32_t hdr[4];
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "GTMLP1\0\0", 8) == 0 && fread(hdr, 4, 4, f) == 4 &&
+            hdr[0] == kMlpIn && hdr[1] == kMlpHidden && hdr[2] == kMlpOut && hdr[3] == kMlpParams;
+  if (ok) {
+    mdl.params.resize(kMlpParams);
+    mdl.fmin.resize(kMlpIn);
+    mdl.fmax.resize(kMlpIn);
+    ok = fread(mdl.params.data(), 4, kMlpParams, f) == (size_t)kMlpParams &&
+         fread(mdl.fmin.data(), 4, kMlpIn, f) == (size_t)kMlpIn && fread(mdl.fmax.data(), 4, kMlpIn, f) == (size_t)kMlpIn;
+  }
+  fclose(f);
+  return ok;
+}
+
+static bool in_training_range(const MlpModel &mdl, const float *x) {
+  for (int k = 0; k < kMlpIn; ++k) {
+    const float span = mdl.fmax[k] - mdl.fmin[k];
+    const float margin = 0.1f * span + 0.01f;
+    if (!(x[k] >= mdl.fmin[k] - margin && x[k] <= mdl.fmax[k] + margin)) return false;
+  }
+  return true;
+}
+
+// Learned choice for every graph: the MLP's forward pass on the device, the
+// argmin over the predicted run times on the host.  Graphs whose features
+// leave the training range keep the heuristic.
+static gt_status mlp_choose(gt_plan_st *plan, int32_t count, const MlpModel &mdl, char *mbase, hipStream_t st) {
+  float *dparams = reinterpret_cast<float *>(mbase);
+  float *dx = dparams + kMlpParams;
+  float *dy = dx + (size_t)count * kMlpIn;
+  std::vector<float> x((size_t)count * kMlpIn), y((size_t)count * kMlpOut);
+  for (int32_t i = 0; i < count; ++i)
+    for (int k = 0; k < kMlpIn; ++k) x[(size_t)i * kMlpIn + k] = plan->graphs[i].features[k];
+  if (hipMemcpyAsync(dparams, mdl.params.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dx, x.data(), sizeof(float) * x.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      mlp_forward(dparams, dx, count, dy, st) != hipSuccess ||
+      hipMemcpyAsync(y.data(), dy, sizeof(float) * y.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GT_ERR_HIP;
+  for (int32_t i = 0; i < count; ++i) {
+    GraphPlan &p = plan->graphs[i];
+    if (!in_training_range(mdl, p.features)) continue;
+    int best = 0;
+    for (int c = 1; c < kMlpOut; ++c)
+      if (y[(size_t)i * kMlpOut + c] < y[(size_t)i * kMlpOut + best]) best = c;
+    config_params(best, &p.fine_bits, &p.digit_bits, &p.variant);
+    p.learned = true;
+    p.config = best;
+  }
+  return GT_OK;
+}
+
 gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count, const gt_options_t &opt,
                         void *workspace, size_t workspace_bytes, hipStream_t st) {
-  (void)workspace; (void)workspace_bytes; (void)st;
   for (int32_t i = 0; i < count; ++i) {
     GraphPlan &p = plan->graphs[i];
     p = GraphPlan{};
     p.n = graphs[i].n;
     p.m = graphs[i].m;
     p.pay = graphs[i].payload != nullptr;
-    heuristic(p);
     p.force_wide = (opt.flags & GT_FLAG_WIDE_STATUS) != 0;
+    p.config = -1;
+    heuristic(p);
     if (opt.policy == GT_POLICY_FIXED) {
       if (opt.fine_bits) p.fine_bits = opt.fine_bits;
       if (opt.digit_bits) p.digit_bits = opt.digit_bits;
       if (opt.variant) p.variant = opt.variant;
+    }
+  }
+  if (opt.policy == GT_POLICY_HEURISTIC || opt.policy == GT_POLICY_MLP) {
+    char *base = scratch_base(graphs, count, workspace, workspace_bytes);
+    if (base == nullptr) return GT_ERR_WORKSPACE_TOO_SMALL;
+    gt_status s = sample_features(plan, graphs, count, opt.seed ? opt.seed : 0x5eedull, base, st);
+    if (s != GT_OK) return s;
+    if (opt.policy == GT_POLICY_MLP) {
+      MlpModel mdl;
+      if (load_model(opt.model_path, mdl)) {
+        size_t off = 0;
+        for (int32_t i = 0; i < count; ++i) off += align256(sample_scratch_bytes(graphs[i].n, graphs[i].m));
+        s = mlp_choose(plan, count, mdl, base + off, st);
+        if (s != GT_OK) return s;
+      }
     }
   }
   return GT_OK;
@@ -54,3 +176,85 @@ gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc
 }
 
 }  // namespace gt
+
+using namespace gt;
+
+extern "C" {
+
+int32_t gt_num_configs(void) { return kMlpOut; }
+
+gt_status gt_config(int32_t idx, int32_t *fine_bits, int32_t *digit_bits, int32_t *variant) {
+  if (idx < 0 || idx >= kMlpOut) return GT_ERR_INVALID_ARGUMENT;
+  int fb, db, v;
+  config_params(idx, &fb, &db, &v);
+  if (fine_bits) *fine_bits = fb;
+  if (digit_bits) *digit_bits = db;
+  if (variant) *variant = v;
+  return GT_OK;
+}
+
+gt_status gt_plan_features(gt_plan_t plan, int32_t i, float *out, int32_t nmax, int32_t *nout) {
+  if (plan == nullptr || i < 0 || i >= plan->count || out == nullptr || nout == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  const GraphPlan &p = plan->graphs[i];
+  const int32_t k = std::min<int32_t>(nmax, p.nfeatures);
+  for (int32_t j = 0; j < k; ++j) out[j] = p.features[j];
+  *nout = p.nfeatures;
+  return GT_OK;
+}
+
+// Time every configuration on one graph (median of `reps` timed runs after
+// one warm-up, HIP events on `stream`); ms_out[c] for c < gt_num_configs().
+// The output buffers receive the (identical) transposition.  Synchronous.
+gt_status gt_autotune(const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t workspace_bytes, void *stream,
+                      int32_t reps, float *ms_out) {
+  if (g == nullptr || out == nullptr || workspace == nullptr || ms_out == nullptr || reps < 1)
+    return GT_ERR_INVALID_ARGUMENT;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return GT_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return GT_ERR_HIP; }
+  gt_status status = GT_OK;
+  std::vector<float> t(reps);
+  for (int c = 0; c < kMlpOut && status == GT_OK; ++c) {
+    gt_options_t o{};
+    o.policy = GT_POLICY_FIXED;
+    config_params(c, &o.fine_bits, &o.digit_bits, &o.variant);
+    gt_plan_t plan = nullptr;
+    status = gt_plan(g, 1, &o, workspace, workspace_bytes, stream, &plan);
+    if (status != GT_OK) break;
+    status = gt_transpose(plan, g, out, workspace, workspace_bytes, stream);
+    for (int r = 0; r < reps && status == GT_OK; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) { status = GT_ERR_HIP; break; }
+      status = gt_transpose(plan, g, out, workspace, workspace_bytes, stream);
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
+        status = GT_ERR_HIP;
+    }
+    gt_plan_destroy(plan);
+    if (status != GT_OK) break;
+    std::vector<float> s(t);
+    std::sort(s.begin(), s.end());
+    ms_out[c] = s[reps / 2];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return status;
+}
+
+// Replace the parameters of graph i of a plan by configuration `config`
+// (e.g. the autotuner's best); the plan's workspace size may grow.
+gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config) {
+  if (plan == nullptr || i < 0 || i >= plan->count || config < 0 || config >= kMlpOut) return GT_ERR_INVALID_ARGUMENT;
+  GraphPlan &p = plan->graphs[i];
+  config_params(config, &p.fine_bits, &p.digit_bits, &p.variant);
+  p.config = config;
+  size_t base = 256;
+  for (int32_t k = 0; k < plan->count; ++k) {
+    finalize_params(plan->graphs[k], base);
+    base = align256(plan->graphs[k].ws_end);
+  }
+  plan->ws_bytes = base;
+  return GT_OK;
+}
+
+}  // extern "C"

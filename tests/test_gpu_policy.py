@@ -1,0 +1,132 @@
+"""GPU: sampling features, MLP kernels and the parameter policies against
+their oracles.  Every case prints its name before it runs."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from oracle import features as OF
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev_graph(O, D, P, dev):
+    O_t = torch.from_numpy(np.ascontiguousarray(O)).to(dev)
+    D_t = torch.from_numpy(np.ascontiguousarray(D)).to(dev)
+    P_t = torch.from_numpy(np.ascontiguousarray(P).view(np.int32)).to(dev) if P is not None else None
+    return O_t, D_t, P_t
+
+
+def graphs():
+    rng = np.random.default_rng(4)
+    n = 30000
+    star = (np.arange(0, 3 * n + 1, 3, dtype=np.int64), np.full(3 * n, 11, dtype=np.int32), None)
+    cyc = (np.arange(n + 1, dtype=np.int64), ((np.arange(n) + 1) % n).astype(np.int32), None)
+    return {
+        "rmat16": gen.workload("rmat16"),
+        "rmat18p": gen.rmat(18, 16, seed=2, permute=True, payload=True),
+        "uniform17": gen.uniform(1 << 17, 8, seed=3),
+        "geom17": gen.geometric(1 << 17, 16, seed=3, p=0.01),
+        "star": star,
+        "cycle": cyc,
+        "empty": (np.zeros(101, dtype=np.int64), np.zeros(0, dtype=np.int32), None),
+    }
+
+
+@pytest.mark.parametrize("name", ["rmat16", "rmat18p", "uniform17", "geom17", "star", "cycle", "empty"])
+def test_features_match_oracle(hip_device, name):
+    import paper_2501_06872_amd as gt
+    O, D, P = graphs()[name]
+    say(f"[case] features {name} n={O.size - 1} m={D.size}")
+    g = dev_graph(O, D, P, hip_device)
+    plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77))
+    got = np.array(plan.features(), dtype=np.float32)
+    ref = OF.features(O, D, P is not None, seed=77)
+    assert got.shape == ref.shape
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-6), (got, ref)
+
+
+def test_mlp_kernels_match_fp64_reference(hip_device):
+    import paper_2501_06872_amd as gt
+    say("[case] mlp forward/gradient/adam")
+    rng = np.random.default_rng(5)
+    p = (OM.init_params(rng) + rng.normal(0, 0.05, OM.NUM_PARAMS)).astype(np.float32)
+    x = rng.random((37, 16)).astype(np.float32)
+    t = rng.normal(size=(37, 32)).astype(np.float32)
+    P_t = torch.from_numpy(p).to(hip_device)
+    X_t = torch.from_numpy(x).to(hip_device)
+    T_t = torch.from_numpy(t).to(hip_device)
+    y = gt.mlp_forward(P_t, X_t).cpu().numpy()
+    ry, _ = OM.forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.allclose(y, ry, rtol=1e-5, atol=1e-5)
+    y2, g, loss = gt.mlp_gradient(P_t, X_t, T_t)
+    rg = OM.gradient(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    g = g.cpu().numpy()
+    assert np.all(np.abs(g - rg) <= 1e-4 * np.maximum(1.0, np.abs(rg)))
+    assert abs(loss.item() - OM.loss(p.astype(np.float64), x, t)) <= 1e-5 * max(1.0, loss.item())
+    m1 = torch.zeros_like(P_t)
+    m2 = torch.zeros_like(P_t)
+    G_t = torch.from_numpy(rg.astype(np.float32)).to(hip_device)
+    gt.mlp_adam(P_t, G_t, m1, m2, 1, 1e-3)
+    rp, _, _ = OM.adam_step(p.astype(np.float64), rg.astype(np.float32).astype(np.float64), np.zeros_like(rg),
+                            np.zeros_like(rg), 1, 1e-3)
+    assert np.allclose(P_t.cpu().numpy(), rp, atol=1e-6)
+
+
+def test_mlp_policy_picks_argmin_and_falls_back(hip_device):
+    import paper_2501_06872_amd as gt
+    from paper_2501_06872_amd import mlp_model
+    say("[case] mlp policy")
+    O, D, P = gen.rmat(17, 16, seed=6, permute=True)
+    g = dev_graph(O, D, P, hip_device)
+    rng = np.random.default_rng(7)
+    p = (OM.init_params(rng) + rng.normal(0, 0.1, OM.NUM_PARAMS)).astype(np.float32)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        mlp_model.save(path, p, np.full(16, -10.0), np.full(16, 10.0))
+        plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_MLP, seed=77, model_path=path))
+        feats = np.array(plan.features(), dtype=np.float64)
+        y, _ = OM.forward(p.astype(np.float64), feats[None, :])
+        best = int(np.argmin(y[0]))
+        cfg = gt.config(best)
+        got = plan.params()
+        assert (got["fine_bits"], got["variant"]) == (cfg["fine_bits"], cfg["variant"])
+        T, S, Q = plan.run(*g)
+        torch.cuda.synchronize()
+        import oracle
+        rT, rS, _ = oracle.transpose(O, D)
+        assert np.array_equal(T.cpu().numpy(), rT) and np.array_equal(S.cpu().numpy(), rS)
+        # features outside the training range keep the heuristic choice
+        mlp_model.save(path, p, np.full(16, 5.0), np.full(16, 5.0))
+        plan2 = gt.Plan([g], gt.make_options(policy=gt.POLICY_MLP, seed=77, model_path=path))
+        plan3 = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77))
+        assert plan2.params() == plan3.params()
+
+
+def test_autotune_every_config_same_output(hip_device):
+    import paper_2501_06872_amd as gt
+    import oracle
+    say("[case] autotune rmat15p")
+    O, D, P = gen.rmat(15, 8, seed=8, permute=True, payload=True)
+    g = dev_graph(O, D, P, hip_device)
+    ms, (T, S, Q) = gt.autotune(*g, reps=3)
+    assert len(ms) == gt.num_configs() and all(t > 0 for t in ms)
+    torch.cuda.synchronize()
+    rT, rS, rQ = oracle.transpose(O, D, P)
+    assert np.array_equal(T.cpu().numpy(), rT) and np.array_equal(S.cpu().numpy(), rS)
+    assert np.array_equal(Q.cpu().numpy().view(np.uint32), rQ)
+    plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_FIXED))
+    for c in (int(np.argmin(ms)), 0, 31):
+        plan.set_config(0, c)
+        T, S, Q = plan.run(*g)
+        torch.cuda.synchronize()
+        assert np.array_equal(S.cpu().numpy(), rS) and np.array_equal(Q.cpu().numpy().view(np.uint32), rQ)
