@@ -29,6 +29,7 @@ WORKLOADS = {
     "geom26": "geometric locality, 2^26 vertices, out-degree 16, dst = src + Geometric(0.01) mod n",
     "rmat28p": "R-MAT scale 28, edge factor 16, g500 probabilities, permuted IDs, no payload",
     "rmat16": "R-MAT scale 16, edge factor 16, g500 probabilities, seed 1",
+    "batch512": "512 uneven graphs (2^10..2^22 vertices, ef 4..32, R-MAT/uniform/geometric, half with payload)",
 }
 # same family at a size the single-threaded oracle finishes in ~10-30 s
 CPU_SAMPLE = {
@@ -86,6 +87,90 @@ def cpu_baseline(workload):
             "sample": f"{desc}: m={m} edges, one full oracle run of {dt:.2f} s"}
 
 
+def bench_batch(args):
+    """Batched + learned (one captured HIP graph, MLP-chosen parameters)
+    against plain per-graph launches (heuristic plans, one stream)."""
+    import torch
+    import gen
+    import paper_2501_06872_amd as gt
+    from paper_2501_06872_amd import mlp_model
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    import concurrent.futures
+    specs = gen.batch_specs(512, seed=5)
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:  # the generator releases the GIL
+        host = list(pool.map(gen.from_spec, specs))
+    m_total = sum(D.size for _, D, _ in host)
+    n_total = sum(O.size - 1 for O, _, _ in host)
+    print(f"[bench] batch512: {len(host)} graphs, n={n_total} m={m_total}, generated in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    graphs = [(torch.from_numpy(O).to(dev), torch.from_numpy(D).to(dev),
+               torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None) for O, D, P in host]
+    torch.cuda.synchronize()
+    # plain: one heuristic plan per graph, launches one graph after another
+    shared = torch.empty(max(gt.workspace_bytes([g]) for g in graphs), dtype=torch.uint8, device=dev)
+    tp = time.time()
+    plains = [gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC), workspace=shared) for g in graphs]
+    plan_plain_s = time.time() - tp
+    outs_p = [p.alloc_out(0, g[2].dtype if g[2] is not None else None) for p, g in zip(plains, graphs)]
+
+    def run_plain():
+        for p, g, o in zip(plains, graphs, outs_p):
+            p.run(*g, out=o)
+
+    # batched + learned: one plan for all graphs, one captured HIP graph
+    model = mlp_model.DEFAULT_PATH
+    policy = gt.POLICY_MLP if os.path.exists(model) else gt.POLICY_HEURISTIC
+    tp = time.time()
+    bplan = gt.Plan(graphs, gt.make_options(policy=policy, model_path=model))
+    plan_batched_s = time.time() - tp
+    outs_b = [bplan.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(graphs)]
+    for _ in range(args.warmup):
+        run_plain()
+        bplan.run_batched(graphs, outs_b)
+    torch.cuda.synchronize()
+    hg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(hg):
+        bplan.run_batched(graphs, outs_b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        run_plain()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / args.steps
+    e0.record(stream)
+    for _ in range(args.steps):
+        hg.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / args.steps
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and
+               (a[2] is None or torch.equal(a[2], b[2])) for a, b in zip(outs_p, outs_b))
+    res = {
+        "metric": "batched+learned speedup over plain per-graph launches",
+        "value": round(ms_plain / ms_batched, 3),
+        "unit": "x",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch512", "description": WORKLOADS["batch512"], "graphs": len(graphs),
+                   "n": n_total, "m": m_total, "policy": "mlp" if policy == gt.POLICY_MLP else "heuristic"},
+        "plain_ms": round(ms_plain, 4),
+        "batched_ms": round(ms_batched, 4),
+        "plain_ges": round(m_total / (ms_plain * 1e-3) / 1e9, 3),
+        "batched_ges": round(m_total / (ms_batched * 1e-3) / 1e9, 3),
+        "plan_s": {"plain": round(plan_plain_s, 3), "batched": round(plan_batched_s, 3)},
+        "end_to_end_speedup_incl_planning": round((ms_plain + plan_plain_s * 1e3) / (ms_batched + plan_batched_s * 1e3),
+                                                  3),
+        "outputs_identical": bool(same),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +189,8 @@ def main():
         print(f"bench.py measures one GPU only (the path is a single-GPU kernel pipeline); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch512":
+        return bench_batch(args)
 
     import torch
     import gen

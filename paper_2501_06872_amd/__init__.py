@@ -141,7 +141,7 @@ class Plan:
     graph) or ``run_batched`` (all graphs) with tensors of the same sizes.
     """
 
-    def __init__(self, graphs, options=None, device=None):
+    def __init__(self, graphs, options=None, device=None, workspace=None):
         L = lib()
         self.device = device if device is not None else graphs[0][0].device
         self.count = len(graphs)
@@ -151,7 +151,10 @@ class Plan:
         self._shapes = [(g[0].numel() - 1, g[1].numel(), g[2] is not None) for g in graphs]
         ws = ctypes.c_size_t(0)
         _check(L.gt_workspace_size(arr, self.count, ctypes.byref(ws)), "gt_workspace_size")
-        self.workspace = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device=self.device)
+        if workspace is not None and workspace.numel() >= int(ws.value):
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         opts = options if options is not None else make_options()
         _check(L.gt_plan(arr, self.count, ctypes.byref(opts), self.workspace.data_ptr(), self.workspace.numel(),
@@ -228,6 +231,14 @@ class Plan:
         if h is not None and _lib is not None:
             _lib.gt_plan_destroy(h)
             self.handle = None
+
+
+def workspace_bytes(graphs):
+    """Workspace bytes for a list of (offsets, indices, payload) graphs."""
+    arr = (CSR * len(graphs))(*[_csr(*g) for g in graphs])
+    ws = ctypes.c_size_t(0)
+    _check(lib().gt_workspace_size(arr, len(graphs), ctypes.byref(ws)), "gt_workspace_size")
+    return int(ws.value)
 
 
 def transpose(offsets, indices, payload=None, options=None):

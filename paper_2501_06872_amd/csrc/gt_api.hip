@@ -63,6 +63,11 @@ void finalize_params(GraphPlan &p, size_t base) {
   }
   p.max_bits = maxbits;
   p.total_bits = dbits;
+  // The 16-wave tiles have no 10-bit instance (their lane-mask tables would
+  // not fit LDS): such plans use the 8-wave x 16-edge tile for every pass, so
+  // that one tile size holds for the tile sources, the look-back status
+  // words and every pass's grid.
+  p.variant = lsd_variant_for(p.variant, maxbits);
   p.nbins_total = int64_t(1) << dbits;
   p.nbins = (p.n + (int64_t(1) << fb) - 1) >> fb;
   if (p.n == 0) p.nbins = 0;
@@ -246,6 +251,9 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
 
 gt_plan_st::~gt_plan_st() {
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : lane_events) (void)hipEventDestroy(e);
+  if (fork_event) (void)hipEventDestroy(fork_event);
+  for (hipStream_t s : lanes) (void)hipStreamDestroy(s);
 }
 
 extern "C" {

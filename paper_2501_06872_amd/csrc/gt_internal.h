@@ -68,6 +68,9 @@ struct FinalArgs {
 };
 
 int64_t lsd_tile_size(int variant);
+// The tile variant that runs digits of up to max_bits bits (variants without
+// an instance for that width map to variant 1).
+int lsd_variant_for(int variant, int max_bits);
 hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide_status,
                       hipStream_t st);
 int64_t final_tile_size();

@@ -659,21 +659,30 @@ int64_t lsd_tile_size(int variant) {
   }
 }
 
+int lsd_variant_for(int variant, int max_bits) {
+  if (variant < 1 || variant > 4) return 1;
+  if ((variant == 2 || variant == 4) && max_bits > 9) return 1;
+  return variant;
+}
+
+// Every (variant, digit width) pair runs an instance whose tile is
+// lsd_tile_size(variant); a pair without one is refused rather than run with
+// another tile size than the plan sized its buffers for.
 hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide,
                       hipStream_t st) {
   if (a.m <= 0) return hipSuccess;
+  if (rbits < 1 || rbits > 10 || lsd_variant_for(variant, rbits) != variant) return hipErrorInvalidValue;
   const int rb = rbits <= 8 ? 8 : (rbits <= 9 ? 9 : 10);
 #define GT_V(W, I)                                                                       \
   return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, wide, st)                      \
                  : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, wide, st)           \
                             : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, wide, st))
   switch (variant) {
-    case 2:  // 16 waves: the 10-bit lane-mask tables would not fit LDS; same tile as variant 1
-      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, wide, st);
-      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, wide, st) : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, wide, st);
+    case 2:  // 16 waves x 8 edges, digits of up to 9 bits
+      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, wide, st)
+                     : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, wide, st);
     case 3: GT_V(8, 8);
-    case 4:  // 16 waves x 16 edges: 16K-edge tiles (10-bit digits fall back to 8 waves x 32 edges? no: 8 x 16)
-      if (rb == 10) return launch_lsd_t<8, 16, 10>(a, csr_in, pay, last, wide, st);
+    case 4:  // 16 waves x 16 edges (16K-edge tiles), digits of up to 9 bits
       return rb == 8 ? launch_lsd_t<16, 16, 8>(a, csr_in, pay, last, wide, st)
                      : launch_lsd_t<16, 16, 9>(a, csr_in, pay, last, wide, st);
     default: GT_V(8, 16);

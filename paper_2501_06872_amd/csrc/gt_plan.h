@@ -63,6 +63,12 @@ struct gt_plan_st {
   std::vector<gt::GraphPlan> graphs;
   size_t ws_bytes;
   gt::Profiler prof;
+  // batched launches: graphs spread over internal streams (default
+  // priority), forked from and joined back into the caller's stream
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> lane_events;
+  hipEvent_t fork_event = nullptr;
+  std::vector<int> lane_of;  // graph -> lane
   ~gt_plan_st();
 };
 

@@ -166,11 +166,57 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
   return GT_OK;
 }
 
+// Batched launch: graphs are spread over kLanes internal streams (largest
+// first, each to the least loaded lane), forked from the caller's stream by
+// one event and joined back by one event per lane, so the kernels of small
+// graphs run concurrently.  Everything is enqueued without a host
+// synchronisation, so the whole batch can be captured into one HIP graph.
+constexpr int kLanes = 8;
+
+static gt_status ensure_lanes(gt_plan_st *plan) {
+  if (!plan->lanes.empty()) return GT_OK;
+  const int nl = std::min<int>(kLanes, std::max<int32_t>(plan->count, 1));
+  for (int i = 0; i < nl; ++i) {
+    hipStream_t s;
+    hipEvent_t e;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GT_ERR_HIP;
+    plan->lanes.push_back(s);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return GT_ERR_HIP;
+    plan->lane_events.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&plan->fork_event, hipEventDisableTiming) != hipSuccess) return GT_ERR_HIP;
+  // assignment: largest graphs first, each to the lane with the least edges
+  std::vector<int> order(plan->count);
+  for (int i = 0; i < plan->count; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return plan->graphs[a].m > plan->graphs[b].m; });
+  std::vector<double> load(nl, 0.0);
+  plan->lane_of.assign(plan->count, 0);
+  for (int i : order) {
+    int best = 0;
+    for (int l = 1; l < nl; ++l) if (load[l] < load[best]) best = l;
+    plan->lane_of[i] = best;
+    load[best] += (double)plan->graphs[i].m + 1e5;  // per-graph fixed cost
+  }
+  return GT_OK;
+}
+
 gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
                           hipStream_t st) {
+  gt_status s = ensure_lanes(plan);
+  if (s != GT_OK) return s;
+  if (launch_fill(reinterpret_cast<uint32_t *>(ws), 1, 0u, st) != hipSuccess) return GT_ERR_HIP;
+  if (hipEventRecord(plan->fork_event, st) != hipSuccess) return GT_ERR_HIP;
+  for (hipStream_t l : plan->lanes)
+    if (hipStreamWaitEvent(l, plan->fork_event, 0) != hipSuccess) return GT_ERR_HIP;
+  Profiler *prof = nullptr;  // per-kernel events are recorded for single-stream launches only
   for (int32_t i = 0; i < plan->count; ++i) {
-    gt_status s = enqueue_graph(plan->graphs[i], graphs[i], outs[i], ws, plan->validate, i == 0, &plan->prof, st);
+    s = enqueue_graph(plan->graphs[i], graphs[i], outs[i], ws, plan->validate, false, prof,
+                      plan->lanes[plan->lane_of[i]]);
     if (s != GT_OK) return s;
+  }
+  for (size_t l = 0; l < plan->lanes.size(); ++l) {
+    if (hipEventRecord(plan->lane_events[l], plan->lanes[l]) != hipSuccess) return GT_ERR_HIP;
+    if (hipStreamWaitEvent(st, plan->lane_events[l], 0) != hipSuccess) return GT_ERR_HIP;
   }
   return GT_OK;
 }
