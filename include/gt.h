@@ -73,8 +73,7 @@ typedef struct {
 enum {
   GT_POLICY_HEURISTIC = 0,  /* sizes and sampled degree features (default) */
   GT_POLICY_FIXED = 1,      /* use fine_bits / digit_bits / variant as given */
-  GT_POLICY_MLP = 2,        /* learned choice from sampled features (falls back to HEURISTIC) */
-  GT_POLICY_TABLE = 3       /* autotuned table lookup by graph size class */
+  GT_POLICY_MLP = 2         /* learned choice from sampled features (falls back to HEURISTIC) */
 };
 
 /* Options; pass NULL for defaults.  Fields set to 0 take their default. */
@@ -95,8 +94,19 @@ enum { GT_FLAG_WIDE_STATUS = 1 };
 
 typedef struct gt_plan_st *gt_plan_t;
 
-/* Bytes of workspace needed to transpose `count` graphs (any policy). */
+/* Bytes of workspace that suffice for gt_plan and for transposing `count`
+ * graphs with any parameters any policy can pick (an upper bound). */
 gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out);
+
+/* Bytes of workspace gt_plan needs for `count` graphs: the degree-sampling
+ * scratch and the learned policy's inputs (the HEURISTIC and MLP policies;
+ * the FIXED policy touches no workspace while planning). */
+gt_status gt_plan_scratch_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out);
+
+/* Bytes of workspace gt_transpose / gt_transpose_batched need with the
+ * parameters this plan holds (at most gt_workspace_size(); may change after
+ * gt_plan_set_config). */
+gt_status gt_plan_workspace_size(gt_plan_t plan, size_t *bytes_out);
 
 /* Build a plan for `count` graphs (count == 1 for gt_transpose).  When the
  * policy needs sampled features the sampling kernels run on `stream` using
@@ -153,7 +163,8 @@ gt_status gt_autotune(const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t 
                       int32_t reps, float *ms_out);
 
 /* Use configuration `config` for graph i of a plan (e.g. the autotuner's
- * best).  The required workspace never exceeds gt_workspace_size(). */
+ * best).  The plan's workspace need (gt_plan_workspace_size) may change; it
+ * never exceeds gt_workspace_size(). */
 gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config);
 
 /* ---- The learned parameter choice: MLP 16 -> 64 -> 64 -> 32 (ReLU, fp32),

@@ -21,11 +21,11 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 
 GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP = \
     range(6)
-POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP, POLICY_TABLE = range(4)
+POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
 
 # Every entry point declared in include/gt.h.
-EXPORTS = ("gt_workspace_size", "gt_plan", "gt_transpose", "gt_transpose_batched", "gt_device_status",
-           "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
+EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
+           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
 NUM_FEATURES = 16
@@ -65,6 +65,8 @@ def lib():
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         P = ctypes.POINTER
         L.gt_workspace_size.argtypes = [P(CSR), i32, P(sz)]
+        L.gt_plan_scratch_size.argtypes = [P(CSR), i32, P(sz)]
+        L.gt_plan_workspace_size.argtypes = [vp, P(sz)]
         L.gt_plan.argtypes = [P(CSR), i32, P(Options), vp, sz, vp, P(vp)]
         L.gt_transpose.argtypes = [vp, P(CSR), P(CSC), vp, sz, vp]
         L.gt_transpose_batched.argtypes = [vp, i32, P(CSR), P(CSC), vp, sz, vp]
@@ -149,17 +151,35 @@ class Plan:
             _check_inputs(*g)
         arr = (CSR * self.count)(*[_csr(*g) for g in graphs])
         self._shapes = [(g[0].numel() - 1, g[1].numel(), g[2] is not None) for g in graphs]
+        # planning needs the sampling scratch only; the transposition needs
+        # what the chosen parameters need (gt_plan_workspace_size)
         ws = ctypes.c_size_t(0)
-        _check(L.gt_workspace_size(arr, self.count, ctypes.byref(ws)), "gt_workspace_size")
-        if workspace is not None and workspace.numel() >= int(ws.value):
-            self.workspace = workspace
-        else:
-            self.workspace = torch.empty(max(int(ws.value), 256), dtype=torch.uint8, device=self.device)
+        _check(L.gt_plan_scratch_size(arr, self.count, ctypes.byref(ws)), "gt_plan_scratch_size")
+        self.workspace = self._buffer(int(ws.value), workspace)
         h = ctypes.c_void_p()
         opts = options if options is not None else make_options()
         _check(L.gt_plan(arr, self.count, ctypes.byref(opts), self.workspace.data_ptr(), self.workspace.numel(),
                          _stream_ptr(self.device), ctypes.byref(h)), "gt_plan")
         self.handle = h
+        self._fit_workspace(workspace)
+
+    def _buffer(self, nbytes, given=None):
+        if given is not None and given.numel() >= nbytes:
+            return given
+        if getattr(self, "workspace", None) is not None and self.workspace.numel() >= nbytes:
+            return self.workspace
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def workspace_size(self):
+        ws = ctypes.c_size_t(0)
+        _check(lib().gt_plan_workspace_size(self.handle, ctypes.byref(ws)), "gt_plan_workspace_size")
+        return int(ws.value)
+
+    def _fit_workspace(self, given=None):
+        need = self.workspace_size()
+        if self.workspace.numel() < need:
+            self.workspace = None
+            self.workspace = self._buffer(need, given)
 
     def params(self, i=0):
         a, b, c, d = (ctypes.c_int32() for _ in range(4))
@@ -203,6 +223,7 @@ class Plan:
 
     def set_config(self, i, config):
         _check(lib().gt_plan_set_config(self.handle, i, config), "gt_plan_set_config")
+        self._fit_workspace()
 
     def profile(self, enable=True):
         _check(lib().gt_profile(self.handle, int(bool(enable))), "gt_profile")
@@ -263,6 +284,9 @@ def autotune(offsets, indices, payload=None, reps=5, plan=None):
     plan = plan if plan is not None else Plan([(offsets, indices, payload)], make_options(policy=POLICY_FIXED))
     T, S, Q = plan.alloc_out(0, payload.dtype if payload is not None else None)
     g = _csr(offsets, indices, payload)
+    ws = ctypes.c_size_t(0)  # every configuration: the any-parameters bound
+    _check(lib().gt_workspace_size(ctypes.byref(g), 1, ctypes.byref(ws)), "gt_workspace_size")
+    plan.workspace = plan._buffer(int(ws.value))
     o = CSC(T.data_ptr(), S.data_ptr() if S.numel() else None,
             (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
     ms = (ctypes.c_float * num_configs())()

@@ -283,6 +283,20 @@ gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes
   return GT_OK;
 }
 
+gt_status gt_plan_scratch_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out) {
+  if (graphs == nullptr || count <= 0 || bytes_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  for (int32_t i = 0; i < count; ++i)
+    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+  *bytes_out = align_up(plan_scratch_bytes(graphs, count)) + kAlign;
+  return GT_OK;
+}
+
+gt_status gt_plan_workspace_size(gt_plan_t plan, size_t *bytes_out) {
+  if (plan == nullptr || bytes_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  *bytes_out = plan->ws_bytes;
+  return GT_OK;
+}
+
 gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
                   size_t workspace_bytes, void *stream, gt_plan_t *plan_out) {
   if (graphs == nullptr || count <= 0 || plan_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
@@ -290,7 +304,7 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
     if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
   gt_options_t o{};
   if (opt) o = *opt;
-  if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_TABLE) return GT_ERR_INVALID_ARGUMENT;
+  if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_MLP) return GT_ERR_INVALID_ARGUMENT;
   if (o.policy == GT_POLICY_FIXED) {
     if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
         (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 4)

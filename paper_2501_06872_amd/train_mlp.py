@@ -60,7 +60,7 @@ def heuristic_config(n, m):
     return (fb - 6) * 8 + 0 * 2 + 1  # variant 1, 10-bit digits
 
 
-def collect(specs, dev, reps, seed=77):
+def collect(specs, dev, reps, seed=77, verbose=False):
     X, Tm, sizes = [], [], []
     pool = concurrent.futures.ThreadPoolExecutor(8)  # the generator releases the GIL
     futures = [pool.submit(gen.from_spec, spec) for spec in specs]
@@ -69,6 +69,8 @@ def collect(specs, dev, reps, seed=77):
         futures[k] = None
         g = (torch.from_numpy(O).to(dev), torch.from_numpy(D).to(dev),
              torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None)
+        if verbose:
+            log(f"  [graph {k}] n={O.size - 1} m={D.size} spec={specs[k]}")
         feats = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=seed)).features()
         ms, _ = gt.autotune(*g, reps=reps)
         X.append(feats)
@@ -136,13 +138,14 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--verbose", action="store_true", help="name every graph before it is timed")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     t0 = time.time()
     log("[train] collecting training timings")
-    Xtr, Ttr, Str = collect(graph_specs(args.train_graphs, 1001, args.large), dev, args.reps)
+    Xtr, Ttr, Str = collect(graph_specs(args.train_graphs, 1001, args.large), dev, args.reps, verbose=args.verbose)
     log(f"[train] collecting evaluation timings ({time.time() - t0:.0f} s)")
-    Xev, Tev, Sev = collect(graph_specs(args.eval_graphs, 2001, args.large // 2), dev, args.reps)
+    Xev, Tev, Sev = collect(graph_specs(args.eval_graphs, 2001, args.large // 2), dev, args.reps, verbose=args.verbose)
     log(f"[train] training ({time.time() - t0:.0f} s)")
     params, hist = train(Xtr, targets(Ttr), dev, args.steps, args.lr)
     fmin, fmax = Xtr.min(axis=0), Xtr.max(axis=0)
