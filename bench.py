@@ -31,14 +31,14 @@ WORKLOADS = {
     "rmat16": "R-MAT scale 16, edge factor 16, g500 probabilities, seed 1",
     "batch512": "512 uneven graphs (2^10..2^22 vertices, ef 4..32, R-MAT/uniform/geometric, half with payload)",
 }
-# same family at a size the single-threaded oracle finishes in ~10-30 s
+# same family at 2^30 edges for workloads too large for one oracle run
 CPU_SAMPLE = {
     "rmat26": ("rmat", dict(scale=23, ef=16, seed=26, permute=False, payload=False)),
     "rmat26p": ("rmat", dict(scale=23, ef=16, seed=26, permute=True, payload=False)),
     "rmat24p": ("rmat", dict(scale=22, ef=16, seed=2, permute=True, payload=True)),
     "uniform26": ("uniform", dict(n=1 << 23, ef=16, seed=3)),
     "geom26": ("geometric", dict(n=1 << 23, ef=16, seed=3, p=0.01)),
-    "rmat28p": ("rmat", dict(scale=23, ef=16, seed=4, permute=True, payload=False)),
+    "rmat28p": ("rmat", dict(scale=26, ef=16, seed=4, permute=True, payload=False)),
     "rmat16": ("rmat", dict(scale=16, ef=16, seed=1, permute=False, payload=False)),
 }
 
@@ -60,31 +60,66 @@ def kernel_bytes(name, n, m, w, passes):
     return 0
 
 
+KERNEL_SOURCES = ("paper_2501_06872_amd/csrc/gt_kernels.hip", "paper_2501_06872_amd/csrc/gt_device.hpp",
+                  "paper_2501_06872_amd/csrc/gt_internal.h")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (calibrated FETCH_SIZE + WRITE_SIZE), or None if
+    there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"gt_kernels_{workload}.txt")
+    if not os.path.exists(path):
+        return None, None
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    sha, traffic = None, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("kernel_source_sha256="):
+                sha = line.split("=", 1)[1].strip()
+            elif line.startswith("traffic_bytes_per_launch "):
+                k, v = line.split(" ", 1)[1].split("=")
+                traffic[k.strip()] = int(float(v))
+    if sha != h.hexdigest() or kernel not in traffic:
+        return None, os.path.relpath(path, ROOT)
+    return traffic[kernel], os.path.relpath(path, ROOT)
+
+
 def path_alg_bytes(n, m, w):
     """Whole-path algorithmic bytes: read CSR + write CSC + 8 B/vertex of counters."""
     return 2 * (8 * (n + 1) + (4 + w) * m) + 8 * n
 
 
-def cpu_baseline(workload):
+def cpu_baseline(workload, O=None, D=None, P=None):
+    """The oracle (single-threaded C, untuned) timed on this host.  Workloads
+    of up to 2^30 edges: one full oracle run on the bench's own graph
+    (~10-30 s); larger ones: a same-family sample of 2^30 edges."""
     import gen
     import oracle
-    kind, kw = CPU_SAMPLE[workload]
-    if kind == "rmat":
-        O, D, P = gen.rmat(kw["scale"], kw["ef"], seed=kw["seed"], permute=kw["permute"], payload=kw["payload"])
-        desc = f"R-MAT scale {kw['scale']} ef {kw['ef']} (same generator, permute={kw['permute']})"
-    elif kind == "uniform":
-        O, D, P = gen.uniform(kw["n"], kw["ef"], seed=kw["seed"])
-        desc = f"uniform n=2^{int(np.log2(kw['n']))} ef {kw['ef']}"
+    if O is None or D.size > (1 << 30):
+        kind, kw = CPU_SAMPLE[workload]
+        if kind == "rmat":
+            O, D, P = gen.rmat(kw["scale"], kw["ef"], seed=kw["seed"], permute=kw["permute"], payload=kw["payload"])
+            desc = f"R-MAT scale {kw['scale']} ef {kw['ef']} (same generator, permute={kw['permute']})"
+        elif kind == "uniform":
+            O, D, P = gen.uniform(kw["n"], kw["ef"], seed=kw["seed"])
+            desc = f"uniform n=2^{int(np.log2(kw['n']))} ef {kw['ef']}"
+        else:
+            O, D, P = gen.geometric(kw["n"], kw["ef"], seed=kw["seed"], p=kw["p"])
+            desc = f"geometric n=2^{int(np.log2(kw['n']))} ef {kw['ef']}"
     else:
-        O, D, P = gen.geometric(kw["n"], kw["ef"], seed=kw["seed"], p=kw["p"])
-        desc = f"geometric n=2^{int(np.log2(kw['n']))} ef {kw['ef']}"
+        desc = f"the full {workload} graph"
     oracle._load()
     t0 = time.perf_counter()
     oracle.transpose(O, D, P)
     dt = time.perf_counter() - t0
     m = D.size
     return {"value": round(m / dt / 1e9, 4), "unit": "GE/s", "cores": 1, "kind": "oracle",
-            "sample": f"{desc}: m={m} edges, one full oracle run of {dt:.2f} s"}
+            "sample": f"{desc}: m={m} edges, one full oracle run of {dt:.2f} s on one host core"}
 
 
 def bench_batch(args):
@@ -250,6 +285,7 @@ def main():
     dom_bytes = kernel_bytes(dom, n, m, w, params["passes"])
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     b_alg = path_alg_bytes(n, m, w)
+    traffic, traffic_src = measured_traffic(args.workload, dom)
 
     check = None
     if args.check:
@@ -282,14 +318,15 @@ def main():
         "kernel_ms": kernels,
         "kernel_ms_per_step": per_step,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "alg_bytes_per_launch": dom_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4),
+                     "traffic_source": traffic_src},
     }
     if check is not None:
         res["check_sampled_slices"] = check
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(args.workload)
+        res["cpu_baseline"] = cpu_baseline(args.workload, O, D, P)
     print(json.dumps(res), flush=True)
 
 

@@ -27,12 +27,24 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
+__device__ void sample_one(SampleArgs a, int64_t i, unsigned long long *s_acc);
+
 // One thread per sample: position, destination, source (binary search of
 // the offsets), frequency count in an open-addressing table, locality sums,
-// and the sample count of the destination's 256-vertex bin.
-__global__ void k_sample(SampleArgs a) {
+// and the sample count of the destination's 256-vertex bin.  The three
+// locality sums are reduced in LDS, one global atomic per block each.
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+  __shared__ unsigned long long s_acc[3];
+  if (threadIdx.x < 3) s_acc[threadIdx.x] = 0ull;
+  __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.s) return;
+  if (i < a.s) sample_one(a, i, s_acc);
+  __syncthreads();
+  if (threadIdx.x < 3 && s_acc[threadIdx.x] != 0ull)
+    atomicAdd((unsigned long long *)&a.acc[threadIdx.x], s_acc[threadIdx.x]);
+}
+
+__device__ void sample_one(SampleArgs a, int64_t i, unsigned long long *s_acc) {
   const uint64_t q = (uint64_t)a.m / (uint64_t)a.s, r = (uint64_t)a.m % (uint64_t)a.s;
   const uint64_t lo = (uint64_t)i * q + ((uint64_t)i * r) / (uint64_t)a.s;
   const uint64_t hi = (uint64_t)(i + 1) * q + ((uint64_t)(i + 1) * r) / (uint64_t)a.s;
@@ -53,23 +65,37 @@ __global__ void k_sample(SampleArgs a) {
     slot = (slot + 1) & a.mask;
   }
   const uint32_t dist = dst > src ? dst - src : src - dst;
-  atomicAdd((unsigned long long *)&a.acc[0], (unsigned long long)dist);
-  if (dist < 256u) atomicAdd((unsigned long long *)&a.acc[1], 1ull);
-  if (dist < 65536u) atomicAdd((unsigned long long *)&a.acc[2], 1ull);
+  atomicAdd(&s_acc[0], (unsigned long long)dist);
+  if (dist < 256u) atomicAdd(&s_acc[1], 1ull);
+  if (dist < 65536u) atomicAdd(&s_acc[2], 1ull);
   atomicAdd(&a.bins[dst >> 8], 1u);
 }
 
 // Over the table: per log2 bucket of the sample count, the number of
 // destinations and their summed counts; number of distinct destinations.
-__global__ void k_sample_table(SampleArgs a) {
+// Reduced in LDS per block, then one global atomic per nonzero sum.
+__global__ __launch_bounds__(256) void k_sample_table(SampleArgs a) {
+  __shared__ unsigned long long s_keys[32], s_sum[32], s_distinct;
+  if (threadIdx.x < 32) { s_keys[threadIdx.x] = 0ull; s_sum[threadIdx.x] = 0ull; }
+  if (threadIdx.x == 0) s_distinct = 0ull;
+  __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i > (int64_t)a.mask) return;
-  if (a.keys[i] == -1) return;
-  const uint32_t c = a.counts[i];
-  const int j = 31 - __clz(c);
-  atomicAdd((unsigned long long *)&a.acc[8 + j], 1ull);
-  atomicAdd((unsigned long long *)&a.acc[40 + j], (unsigned long long)c);
-  atomicAdd((unsigned long long *)&a.acc[3], 1ull);
+  if (i <= (int64_t)a.mask && a.keys[i] != -1) {
+    const uint32_t c = a.counts[i];
+    const int j = 31 - __clz(c);
+    atomicAdd(&s_keys[j], 1ull);
+    atomicAdd(&s_sum[j], (unsigned long long)c);
+    atomicAdd(&s_distinct, 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int j = threadIdx.x;
+    if (s_keys[j]) {
+      atomicAdd((unsigned long long *)&a.acc[8 + j], s_keys[j]);
+      atomicAdd((unsigned long long *)&a.acc[40 + j], s_sum[j]);
+    }
+  }
+  if (threadIdx.x == 0 && s_distinct) atomicAdd((unsigned long long *)&a.acc[3], s_distinct);
 }
 
 // Over the 256-vertex bins: samples falling in bins whose estimated edge

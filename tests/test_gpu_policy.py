@@ -99,7 +99,7 @@ def test_mlp_policy_picks_argmin_and_falls_back(hip_device):
         best = int(np.argmin(y[0]))
         cfg = gt.config(best)
         got = plan.params()
-        assert (got["fine_bits"], got["variant"]) == (cfg["fine_bits"], cfg["variant"])
+        assert (got["fine_bits"], got["variant"]) == (cfg["fine_bits"], resolved_variant(cfg, got))
         T, S, Q = plan.run(*g)
         torch.cuda.synchronize()
         import oracle
@@ -110,6 +110,48 @@ def test_mlp_policy_picks_argmin_and_falls_back(hip_device):
         plan2 = gt.Plan([g], gt.make_options(policy=gt.POLICY_MLP, seed=77, model_path=path))
         plan3 = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77))
         assert plan2.params() == plan3.params()
+
+
+def resolved_variant(cfg, got):
+    # 16-wave tile variants have no 10-bit instance: such plans run variant 1
+    return 1 if cfg["variant"] in (2, 4) and got["digit_bits"] == 10 else cfg["variant"]
+
+
+def test_committed_model_drives_the_plan(hip_device):
+    import paper_2501_06872_amd as gt
+    import oracle
+    from paper_2501_06872_amd import mlp_model
+    path = mlp_model.DEFAULT_PATH
+    if not os.path.exists(path):
+        pytest.skip("no trained model committed")
+    p, fmin, fmax = mlp_model.load(path)
+    specs = gen.batch_specs(6, seed=4242)
+    for s in specs:
+        s["n"] = max(1024, s["n"] >> 4)
+    for spec in specs:
+        say(f"[case] committed model, spec {spec}")
+        O, D, P = gen.from_spec(spec)
+        g = dev_graph(O, D, P, hip_device)
+        plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_MLP, seed=77, model_path=path))
+        feats = np.array(plan.features(), dtype=np.float64)
+        got = plan.params()
+        span = fmax - fmin
+        inside = np.all((feats >= fmin - 0.1 * span - 0.01) & (feats <= fmax + 0.1 * span + 0.01))
+        if inside:
+            y, _ = OM.forward(p.astype(np.float64), feats[None, :])
+            order = np.argsort(y[0])
+            # fp32 on the device vs fp64 here: accept the runner-up on a near tie
+            near = [int(c) for c in order[:2] if y[0][c] - y[0][order[0]] < 1e-4]
+            ok = [(gt.config(c)["fine_bits"], resolved_variant(gt.config(c), got)) for c in near]
+            assert (got["fine_bits"], got["variant"]) in ok
+        else:
+            assert plan.params() == gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77)).params()
+        T, S, Q = plan.run(*g)
+        torch.cuda.synchronize()
+        rT, rS, rQ = oracle.transpose(O, D, P)
+        assert np.array_equal(T.cpu().numpy(), rT) and np.array_equal(S.cpu().numpy(), rS)
+        if P is not None:
+            assert np.array_equal(Q.cpu().numpy().view(np.uint32), rQ)
 
 
 def test_autotune_every_config_same_output(hip_device):

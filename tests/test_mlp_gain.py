@@ -1,0 +1,90 @@
+"""What the trained parameter-choice network gains over the heuristic.
+
+The committed weights (paper_2501_06872_amd/models/gt_mlp.bin) were trained
+on autotuner timings measured on MI355X; train_metrics_data.npz holds the
+features and the measured run time of every configuration for held-out
+evaluation graphs (seeds disjoint from the training graphs).  Here the
+network's choices are recomputed with the fp64 oracle forward pass and
+scored against those measured timings: the exhaustive autotuner (best time
+per graph) is the judge, the sampling heuristic is the method without the
+network.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MODELS = os.path.join(ROOT, "paper_2501_06872_amd", "models")
+
+
+def heuristic_config(n, m):
+    # the library's heuristic: fine_bits = round(log2(8192 / average in-degree)),
+    # 10-bit digits, tile variant 1; its index in the grid c = (fb-6)*8 + ...
+    fb = int(round(math.log2(8192.0 / max(m / max(n, 1), 1.0))))
+    fb = min(max(fb, 6), 9)
+    return (fb - 6) * 8 + 1
+
+
+def in_range(x, fmin, fmax):
+    span = fmax - fmin
+    margin = 0.1 * span + 0.01
+    return bool(np.all((x >= fmin - margin) & (x <= fmax + margin)))
+
+
+@pytest.fixture(scope="module")
+def stored():
+    from paper_2501_06872_amd import mlp_model
+    path = os.path.join(MODELS, "gt_mlp.bin")
+    data = os.path.join(MODELS, "train_metrics_data.npz")
+    if not (os.path.exists(path) and os.path.exists(data)):
+        pytest.skip("no trained model committed")
+    p, fmin, fmax = mlp_model.load(path)
+    return p, fmin, fmax, np.load(data)
+
+
+def choices(p, fmin, fmax, X, sizes):
+    y, _ = OM.forward(p.astype(np.float64), X.astype(np.float64))
+    pick = y.argmin(axis=1)
+    heur = np.array([heuristic_config(n, m) for n, m in sizes])
+    ok = np.array([in_range(x, fmin, fmax) for x in X])
+    return np.where(ok, pick, heur), heur
+
+
+def test_heuristic_index_matches_the_grid():
+    import paper_2501_06872_amd as gt
+    c = heuristic_config(1 << 20, 16 << 20)  # average degree 16 -> fine_bits 9
+    assert gt.config(c) == dict(fine_bits=9, digit_bits=10, variant=1)
+
+
+def test_trained_network_beats_the_heuristic_on_held_out_graphs(stored):
+    p, fmin, fmax, d = stored
+    X, T, S = d["Xev"], d["Tev"], d["Sev"]
+    assert X.shape[1] == 16 and T.shape[1] == 32 and len(X) >= 40
+    pick, heur = choices(p, fmin, fmax, X, S)
+    rows = np.arange(len(T))
+    best = T.min(axis=1)
+    t_mlp, t_heur = T[rows, pick], T[rows, heur]
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    regret_mlp, regret_heur = gm(t_mlp / best), gm(t_heur / best)
+    gain = gm(t_heur / t_mlp)
+    print(f"held-out graphs {len(T)}: regret mlp {regret_mlp:.4f}, heuristic {regret_heur:.4f}, "
+          f"gain {gain:.4f}, total ms best {best.sum():.2f} mlp {t_mlp.sum():.2f} heuristic {t_heur.sum():.2f}")
+    assert regret_mlp < regret_heur
+    assert gain > 1.0
+    assert t_mlp.sum() < t_heur.sum()
+    assert regret_mlp < 1.05  # within 5% of the exhaustive autotuner
+
+
+def test_training_fit_and_metrics_agree(stored):
+    p, fmin, fmax, d = stored
+    X, T = d["Xtr"], d["Ttr"]
+    L = np.log(T)
+    target = L - L.mean(axis=1, keepdims=True)
+    # the stored weights reach a small loss on their training set
+    assert OM.loss(p, X, target) < 0.01
+    # the feature range stored with the weights is the training range
+    assert np.allclose(fmin, X.min(axis=0)) and np.allclose(fmax, X.max(axis=0))
