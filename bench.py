@@ -57,6 +57,12 @@ def kernel_bytes(name, n, m, w, passes):
         return rd + wr
     if name == "k_final":
         return (4 + 2 + w) * m + (4 + w) * m + 8 * (n + 1)
+    if name == "k_hlh_count":  # read D, write the n counters once
+        return 4 * m + 4 * n
+    if name == "k_scan_offsets":  # read counts, write offsets and cursors
+        return 4 * n + 8 * (n + 1) + 8 * n
+    if name == "k_hlh_scatter":  # read CSR (+ payload), write CSC lists
+        return 4 * m + 8 * (n + 1) + w * m + (4 + w) * m
     return 0
 
 
@@ -216,6 +222,8 @@ def main():
     ap.add_argument("--fine-bits", type=int, default=0)
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--strategy", default="stable", choices=["stable", "hlh", "atomic"],
+                    help="hlh / atomic: the paper's unordered methods (list order left to atomics)")
     ap.add_argument("--check", action="store_true", help="check the output on sampled vertex ranges")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB once before timing (reference for HBM byte counters)")
@@ -241,10 +249,11 @@ def main():
     O_t = torch.from_numpy(O).to(dev)
     D_t = torch.from_numpy(D).to(dev)
     P_t = torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None
-    opts = None
+    strategy = {"stable": gt.STRATEGY_STABLE, "hlh": gt.STRATEGY_HLH, "atomic": gt.STRATEGY_ATOMIC}[args.strategy]
+    opts = gt.make_options(strategy=strategy)
     if args.fine_bits or args.digit_bits or args.variant:
         opts = gt.make_options(policy=gt.POLICY_FIXED, fine_bits=args.fine_bits, digit_bits=args.digit_bits,
-                               variant=args.variant)
+                               variant=args.variant, strategy=strategy)
     plan = gt.Plan([(O_t, D_t, P_t)], opts)
     params = plan.params()
     out = plan.alloc_out(0, P_t.dtype if P_t is not None else None)
@@ -312,7 +321,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": n, "m": m,
-                   "payload_bytes": w, "params": params},
+                   "payload_bytes": w, "strategy": args.strategy,
+                   "params": params if args.strategy == "stable" else None},
         "path_hbm_frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "path_alg_bytes": b_alg,
         "kernel_ms": kernels,

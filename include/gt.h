@@ -86,7 +86,21 @@ typedef struct {
   uint64_t seed;         /* seed of the degree-sampling pass */
   const char *model_path;/* weights of the learned policy (GT_POLICY_MLP) */
   int32_t flags;         /* GT_FLAG_* */
+  int32_t strategy;      /* GT_STRATEGY_* (0 = the stable method) */
+  int32_t hdv_max;       /* GT_STRATEGY_HLH: at most this many HDVs (0 = 2048, the maximum) */
 } gt_options_t;
+
+/* Strategies.  GT_STRATEGY_STABLE (the default) produces every CSC list in
+ * increasing CSR edge position.  The other two are the paper's own methods
+ * and leave the order inside each CSC list to the atomics, as the paper does
+ * (the offsets and the multiset of every list are exact):
+ *   GT_STRATEGY_HLH    PoTra (Section IV, Algorithm 2): HDVs found by a 1%
+ *                      degree sample, counted and placed through per-chunk
+ *                      LDS counters; LDVs through wave-aggregated global
+ *                      atomics.
+ *   GT_STRATEGY_ATOMIC Atomic GT (Algorithm 1): every destination through
+ *                      wave-aggregated global atomics. */
+enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2 };
 
 /* Flags.  GT_FLAG_WIDE_STATUS forces the 64-bit look-back words that graphs
  * with m >= 2^31 use, so that path can be tested on small graphs. */

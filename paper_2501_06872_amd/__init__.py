@@ -22,6 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP = \
     range(6)
 POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
+# STABLE: every CSC list in CSR edge order.  HLH / ATOMIC: the paper's methods,
+# list order left to the atomics (offsets and list contents exact).
+STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC = range(3)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
@@ -49,7 +52,8 @@ class CSC(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("fine_bits", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("validate", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("model_path", ctypes.c_char_p), ("flags", ctypes.c_int32)]
+                ("model_path", ctypes.c_char_p), ("flags", ctypes.c_int32), ("strategy", ctypes.c_int32),
+                ("hdv_max", ctypes.c_int32)]
 
 
 _lib = None
@@ -131,9 +135,9 @@ FLAG_WIDE_STATUS = 1
 
 
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
-                 model_path=None, flags=0):
+                 model_path=None, flags=0, strategy=STRATEGY_STABLE, hdv_max=0):
     return Options(policy, fine_bits, digit_bits, variant, int(bool(validate)), seed,
-                   model_path.encode() if model_path else None, flags)
+                   model_path.encode() if model_path else None, flags, strategy, hdv_max)
 
 
 class Plan:

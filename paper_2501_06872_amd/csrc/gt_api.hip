@@ -12,6 +12,8 @@
 #include "../../include/gt.h"
 #include "gt_internal.h"
 #include "gt_plan.h"
+#include "gt_sample.h"
+#include "gt_unordered.h"
 
 using namespace gt;
 
@@ -40,7 +42,35 @@ namespace gt {
 
 // Derive passes/shifts/bins from (n, m, fine_bits, digit_bits, variant) and
 // lay out the workspace regions of one graph starting at byte `base`.
+// Workspace of the unordered strategies: sampling scratch (HLH), frequency
+// histogram and HDV list, in-degree counters, LDV cursors, per-chunk HDV
+// counts, scan status words.
+size_t unordered_workspace_end(GraphPlan &p, size_t base) {
+  const bool hlh = p.strategy == GT_STRATEGY_HLH;
+  p.kmax = hlh ? (p.hdv_max > 0 && p.hdv_max < kHlhMaxHdv ? p.hdv_max : kHlhMaxHdv) : 0;
+  p.nchunks = p.m > 0 ? std::min<int64_t>(std::max<int64_t>((p.m + 65535) / 65536, 1), 2048) : 0;
+  p.chunk = p.nchunks > 0 ? (p.m + p.nchunks - 1) / p.nchunks : 0;
+  size_t off = base;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  const size_t nv = (size_t)std::max<int64_t>(p.n, 1);
+  p.off_u_samp = hlh ? take(sample_scratch_bytes(p.n, p.m)) : 0;
+  p.off_u_hist = take(4 * (size_t)kHdvHistBins);
+  p.off_u_thr = take(4);
+  p.off_u_hdv = take(4 * (size_t)std::max(p.kmax, 1));
+  p.off_u_nhdv = take(4);
+  p.off_u_cnt = take(4 * nv);
+  p.off_u_cur = take(8 * nv);
+  p.off_u_H = take(4 * (size_t)std::max<int64_t>(p.nchunks, 1) * (size_t)std::max(p.kmax, 1));
+  p.off_u_sstatus = take(8 * (size_t)((p.n + offsets_scan_tile() - 1) / offsets_scan_tile() + 1));
+  p.off_u_ticket = take(4);
+  return off;
+}
+
 void finalize_params(GraphPlan &p, size_t base) {
+  if (p.strategy != GT_STRATEGY_STABLE) {
+    p.ws_end = unordered_workspace_end(p, base);
+    return;
+  }
   const int L = std::max(1, ceil_log2(std::max<int64_t>(p.n, 2)));
   int fb = std::min(p.fine_bits, kMaxFineBits);
   fb = std::min(fb, L - 1);
@@ -126,6 +156,11 @@ size_t graph_workspace_bound(int64_t n, int64_t m, bool pay) {
         finalize_params(p, 0);
         best = std::max(best, p.ws_end);
       }
+  for (int strategy : {GT_STRATEGY_HLH, GT_STRATEGY_ATOMIC}) {
+    GraphPlan p{};
+    p.n = n; p.m = m; p.pay = pay; p.strategy = strategy;
+    best = std::max(best, unordered_workspace_end(p, 0));
+  }
   return best;
 }
 
@@ -166,6 +201,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
     return GT_OK;
   }
   if (validate) GT_CHK(launch_validate_offsets(g.offsets, p.n, p.m, err, st));
+  if (p.strategy != GT_STRATEGY_STABLE) return enqueue_unordered(p, g, out, ws, prof, st);
 
   uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + p.off_ticket);
   uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
@@ -247,6 +283,52 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   return GT_OK;
 }
 
+// The unordered strategies (Atomic GT and HLH): count, aggregate, scatter.
+gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
+                            hipStream_t st) {
+  hipError_t e = hipSuccess;
+#define GT_CHK(x) do { e = (x); if (e != hipSuccess) return GT_ERR_HIP; } while (0)
+#define GT_TIMED(name, x) do { if (prof) GT_CHK(prof->begin(name, st)); GT_CHK(x); if (prof) GT_CHK(prof->end(st)); } while (0)
+  UnorderedArgs u{};
+  u.O = g.offsets; u.D = g.indices; u.P = g.payload;
+  u.n = p.n; u.m = p.m;
+  u.chunk = p.chunk; u.nchunks = p.nchunks;
+  u.kmax = p.kmax;
+  u.log2slots = kHlhLog2Slots;
+  u.hdv = reinterpret_cast<const int32_t *>(ws + p.off_u_hdv);
+  u.cnt = reinterpret_cast<uint32_t *>(ws + p.off_u_cnt);
+  u.H = reinterpret_cast<uint32_t *>(ws + p.off_u_H);
+  u.T = out.offsets; u.S = out.indices; u.Q = out.payload;
+  u.cur = reinterpret_cast<unsigned long long *>(ws + p.off_u_cur);
+  u.err = reinterpret_cast<uint32_t *>(ws);
+  u.scan_status = reinterpret_cast<uint64_t *>(ws + p.off_u_sstatus);
+  u.scan_ticket = reinterpret_cast<uint32_t *>(ws + p.off_u_ticket);
+  GT_CHK(launch_fill(u.cnt, (uint64_t)p.n, 0u, st));
+  if (p.strategy == GT_STRATEGY_HLH) {
+    // Step 0: the degree sample and the HDV list (at most kmax vertices)
+    uint32_t *nhdv = reinterpret_cast<uint32_t *>(ws + p.off_u_nhdv);
+    SampleArgs sa{};
+    float *feat = nullptr;
+    GT_TIMED("k_sample", enqueue_sampling(g.offsets, g.indices, p.n, p.m, p.pay, p.seed, ws + p.off_u_samp, &feat, st,
+                                          &sa));
+    GT_TIMED("k_hdv_select", launch_hdv_select(sa.keys, sa.counts, sa.mask, p.kmax,
+                                               reinterpret_cast<uint32_t *>(ws + p.off_u_hist),
+                                               reinterpret_cast<uint32_t *>(ws + p.off_u_thr),
+                                               reinterpret_cast<int32_t *>(ws + p.off_u_hdv), nhdv, st));
+    u.nhdv = nhdv;
+  }
+  GT_TIMED("k_hlh_count", launch_hlh_count(u, st));
+  GT_TIMED("k_hdv_colscan", launch_hdv_colscan(u, st));
+  const int64_t scan_tiles = (p.n + offsets_scan_tile() - 1) / offsets_scan_tile();
+  GT_CHK(launch_fill(reinterpret_cast<uint32_t *>(u.scan_status), 2 * (uint64_t)scan_tiles, 0u, st));
+  GT_CHK(launch_fill(u.scan_ticket, 1, 0u, st));
+  GT_TIMED("k_scan_offsets", launch_scan_offsets(u, st));
+  GT_TIMED("k_hlh_scatter", launch_hlh_scatter(u, st));
+#undef GT_TIMED
+#undef GT_CHK
+  return GT_OK;
+}
+
 }  // namespace gt
 
 gt_plan_st::~gt_plan_st() {
@@ -305,6 +387,8 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   gt_options_t o{};
   if (opt) o = *opt;
   if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_MLP) return GT_ERR_INVALID_ARGUMENT;
+  if (o.strategy < GT_STRATEGY_STABLE || o.strategy > GT_STRATEGY_ATOMIC || o.hdv_max < 0 || o.hdv_max > kHlhMaxHdv)
+    return GT_ERR_UNSUPPORTED;
   if (o.policy == GT_POLICY_FIXED) {
     if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
         (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 4)

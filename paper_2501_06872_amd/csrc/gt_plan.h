@@ -30,6 +30,13 @@ struct GraphPlan {
   size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big;
   int64_t max_big;
   int64_t max_items;
+  // unordered strategies (GT_STRATEGY_HLH / GT_STRATEGY_ATOMIC)
+  int strategy;
+  int32_t hdv_max, kmax;
+  uint64_t seed;
+  int64_t nchunks, chunk;
+  size_t off_u_samp, off_u_hist, off_u_thr, off_u_hdv, off_u_nhdv, off_u_cnt, off_u_cur, off_u_H, off_u_sstatus,
+      off_u_ticket;
   size_t ws_end;
   // sampled features (when the policy sampled the graph)
   float features[32];
@@ -81,6 +88,9 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
                         void *workspace, size_t workspace_bytes, hipStream_t st);
 gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
                         bool reset_status, Profiler *prof, hipStream_t st);
+size_t unordered_workspace_end(GraphPlan &p, size_t base);
+gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
+                            hipStream_t st);
 gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
                           hipStream_t st);
 

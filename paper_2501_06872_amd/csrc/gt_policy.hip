@@ -141,6 +141,9 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
     p.pay = graphs[i].payload != nullptr;
     p.force_wide = (opt.flags & GT_FLAG_WIDE_STATUS) != 0;
     p.config = -1;
+    p.strategy = opt.strategy;
+    p.hdv_max = opt.hdv_max;
+    p.seed = opt.seed ? opt.seed : 0x5eedull;
     heuristic(p);
     if (opt.policy == GT_POLICY_FIXED) {
       if (opt.fine_bits) p.fine_bits = opt.fine_bits;

@@ -26,7 +26,8 @@ struct SampleArgs {
 
 int64_t sample_count(int64_t n, int64_t m);
 size_t sample_scratch_bytes(int64_t n, int64_t m);
+// `table_out` (optional) receives the frequency table's location.
 hipError_t enqueue_sampling(const int64_t *O, const int32_t *D, int64_t n, int64_t m, bool payload, uint64_t seed,
-                            char *scratch, float **features_dev, hipStream_t st);
+                            char *scratch, float **features_dev, hipStream_t st, SampleArgs *table_out = nullptr);
 
 }  // namespace gt

@@ -166,7 +166,7 @@ size_t sample_scratch_bytes(int64_t n, int64_t m) {
 // Enqueue the sampling kernels of one graph into `scratch`; the features
 // land in *features_dev (kNumFeatures floats inside the scratch region).
 hipError_t enqueue_sampling(const int64_t *O, const int32_t *D, int64_t n, int64_t m, bool payload, uint64_t seed,
-                            char *scratch, float **features_dev, hipStream_t st) {
+                            char *scratch, float **features_dev, hipStream_t st, SampleArgs *table_out) {
   SampleArgs a{};
   a.O = O; a.D = D; a.n = n; a.m = m; a.seed = seed; a.payload = payload;
   a.s = sample_count(n, m);
@@ -196,6 +196,7 @@ hipError_t enqueue_sampling(const int64_t *O, const int32_t *D, int64_t n, int64
     a.s = 1;  // features of an empty graph: sizes only
   }
   hipLaunchKernelGGL(k_features, dim3(1), dim3(64), 0, st, a, feat);
+  if (table_out) *table_out = a;
   return hipGetLastError();
 }
 

@@ -1,0 +1,43 @@
+// Unordered strategies (Atomic GT, HLH): interface between the plan and the
+// kernels of gt_unordered.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+constexpr int kHlhMaxHdv = 2048;    // HDVs held in LDS per workgroup
+constexpr int kHlhLog2Slots = 12;   // table slots (load factor <= 1/2)
+constexpr int kHdvHistBins = 4096;  // sampled frequencies, capped
+
+struct UnorderedArgs {
+  const int64_t *O;
+  const int32_t *D;
+  const uint32_t *P;
+  int64_t n, m;
+  int64_t chunk;      // edges per chunk (one workgroup each, same map in Steps 1 and 3)
+  int64_t nchunks;
+  const int32_t *hdv;     // [kmax] HDV list
+  const uint32_t *nhdv;   // device scalar (NULL: no HDVs, Atomic GT)
+  int32_t kmax;
+  int log2slots;
+  uint32_t *cnt;          // [n] in-degrees
+  uint32_t *H;            // [nchunks][kmax] per-chunk HDV counts -> column prefixes
+  int64_t *T;
+  int32_t *S;
+  uint32_t *Q;
+  unsigned long long *cur;   // [n] LDV cursors
+  uint32_t *err;
+  uint64_t *scan_status;     // [scan tiles]
+  uint32_t *scan_ticket;
+};
+
+hipError_t launch_hdv_select(const int32_t *keys, const uint32_t *counts, uint32_t mask, int32_t kmax,
+                             uint32_t *hist, uint32_t *thr, int32_t *hdv, uint32_t *nhdv, hipStream_t st);
+hipError_t launch_hlh_count(const UnorderedArgs &a, hipStream_t st);
+hipError_t launch_hdv_colscan(const UnorderedArgs &a, hipStream_t st);
+int64_t offsets_scan_tile();
+hipError_t launch_scan_offsets(const UnorderedArgs &a, hipStream_t st);
+hipError_t launch_hlh_scatter(const UnorderedArgs &a, hipStream_t st);
+
+}  // namespace gt
