@@ -47,13 +47,31 @@ __device__ __forceinline__ uint32_t rank_row_lds(uint32_t key, bool ok, uint16_t
   return old + (uint32_t)__popcll(peers & lt);
 }
 
+// Inclusive running maximum across the 64 lanes with DPP moves only (no
+// LDS crossbar): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
+// last lane of row 0 / row 2 into rows 1 / 3 (row_bcast:15) and the last
+// lane of row 1 into rows 2 and 3 (row_bcast:31).  Lanes without a source
+// read 0, the identity of an unsigned maximum.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
 __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t t = __shfl_up(v, o);
-    if (lane >= o) v = v > t ? v : t;
-  }
+  (void)lane;
+  v = umax32(v, dpp_move<0x111, 0xf>(v));  // row_shr:1
+  v = umax32(v, dpp_move<0x112, 0xf>(v));  // row_shr:2
+  v = umax32(v, dpp_move<0x114, 0xf>(v));  // row_shr:4
+  v = umax32(v, dpp_move<0x118, 0xf>(v));  // row_shr:8
+  v = umax32(v, dpp_move<0x142, 0xa>(v));  // row_bcast:15 -> rows 1, 3
+  v = umax32(v, dpp_move<0x143, 0xc>(v));  // row_bcast:31 -> rows 2, 3
   return v;
+}
+
+// The value of lane 63 in every lane (scalar read, no LDS crossbar).
+__device__ __forceinline__ uint32_t wave_last(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, int lane) {

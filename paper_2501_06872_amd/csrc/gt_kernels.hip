@@ -29,6 +29,12 @@
 
 namespace gt {
 
+// Zero `bytes` (a multiple of 16) of 16-byte aligned LDS with 16-byte stores.
+__device__ __forceinline__ void lds_zero16(void *p, int bytes, int tid, int nt) {
+  uint4 *q = static_cast<uint4 *>(p);
+  for (int i = tid; i < bytes / 16; i += nt) q[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   // staging buffer; during ranking it holds the per-wave lane-mask tables
   constexpr int STAGE_WORDS = TILE > 2 * WAVES * RADIX ? TILE : 2 * WAVES * RADIX;
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
-  __shared__ uint16_t s_wcnt[WAVES][RADIX];
+  __shared__ __align__(16) uint16_t s_wcnt[WAVES][RADIX];
   __shared__ uint32_t s_tot[RADIX];
   __shared__ uint32_t s_toff[RADIX];
   __shared__ uint64_t s_gbase[RADIX];
@@ -186,8 +192,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   const int radix = 1 << a.bits;
   const uint32_t dmask = (uint32_t)radix - 1u;
 
-  for (int i = tid; i < WAVES * RADIX; i += NT) (&s_wcnt[0][0])[i] = 0;
-  for (int i = tid; i < 2 * WAVES * RADIX; i += NT) s_stage[i] = 0u;
+  lds_zero16(&s_wcnt[0][0], WAVES * RADIX * 2, tid, NT);
+  lds_zero16(s_stage, 2 * WAVES * RADIX * 4, tid, NT);
   if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
   __syncthreads();
   const int64_t tile = s_tile;
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     if (CSR_IN) {
       // mark the first edge of every source that starts inside the tile, then
       // fill forward (sources increase along the edge array)
-      for (int i = tid; i < TILE; i += NT) s_stage[i] = 0;
+      lds_zero16(s_stage, TILE * 4, tid, NT);
       __syncthreads();
       const int64_t u0 = a.tile_src0[tile];
       if (tid == 0) s_stage[0] = (uint32_t)u0;
@@ -309,24 +315,22 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
         if (o > base) atomicMax(&s_stage[o - base], (uint32_t)u);
       }
       __syncthreads();
+      // running maximum along the wave's rows, kept in registers (each
+      // thread reads exactly the slots of its own edges)
       uint32_t carry = 0;
+#pragma unroll
       for (int r = 0; r < ITEMS; ++r) {
-        const int i = (w * ITEMS + r) * kWave + lane;
-        uint32_t v = wave_incl_max(s_stage[i], lane);
+        uint32_t v = wave_incl_max(s_stage[row_idx(r)], lane);
         v = v > carry ? v : carry;
-        s_stage[i] = v;
-        carry = __shfl(v, kWave - 1);
+        src[r] = v;
+        carry = wave_last(v);
       }
       if (lane == 0) s_misc[w] = carry;
-      __syncthreads();
+      __syncthreads();  // also: every read of the marks is done before staging below
       uint32_t before = 0;
       for (int i = 0; i < w; ++i) before = before > s_misc[i] ? before : s_misc[i];
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t v = s_stage[row_idx(j)];
-        src[j] = v > before ? v : before;
-      }
-      __syncthreads();
+      for (int j = 0; j < ITEMS; ++j) src[j] = src[j] > before ? src[j] : before;
     } else {
       const int32_t *sin = a.in_src + base;
 #pragma unroll
@@ -513,7 +517,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   constexpr int FW = 1 << FBITS;
   constexpr int STAGE_WORDS = TILE > 2 * WAVES * FW ? TILE : 2 * WAVES * FW;
   __shared__ __align__(16) uint32_t s_stage[STAGE_WORDS];
-  __shared__ uint16_t s_wcnt[WAVES][FW];
+  __shared__ __align__(16) uint16_t s_wcnt[WAVES][FW];
   __shared__ uint32_t s_tot[FW];
   __shared__ uint32_t s_toff[FW];
   __shared__ uint64_t s_cur[FW];
@@ -532,8 +536,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   const int64_t v0 = (int64_t)f << a.fine_bits;
   auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
 
-  for (int i = tid; i < WAVES * FW; i += NT) (&s_wcnt[0][0])[i] = 0;
-  for (int i = tid; i < 2 * WAVES * FW; i += NT) s_stage[i] = 0u;
+  lds_zero16(&s_wcnt[0][0], WAVES * FW * 2, tid, NT);
+  lds_zero16(s_stage, 2 * WAVES * FW * 4, tid, NT);
   if (nch > 1) {
     const uint32_t *row = a.cntab + (uint64_t)item * fw;
     for (int v = tid; v < fw; v += NT) s_cur[v] = (uint64_t)a.T[v0 + v < a.n ? v0 + v : a.n] + row[v];
@@ -545,7 +549,10 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   {
     unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FW;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) lpos[j] = rank_row_lds(key[j], row_idx(j) < cnt, s_wcnt[w], tab, lane);
+    for (int j = 0; j < ITEMS; ++j) {
+      if ((w * ITEMS + j) * kWave >= cnt) break;  // the rest of this wave's rows hold no edge
+      lpos[j] = rank_row_lds(key[j], row_idx(j) < cnt, s_wcnt[w], tab, lane);
+    }
   }
   __syncthreads();
   for (int v = tid; v < fw; v += NT) {

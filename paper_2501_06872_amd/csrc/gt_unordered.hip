@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kUNT) void k_hlh_scatter(UnorderedArgs a) {
       uint32_t x = wave_incl_max(s_src[i], lane);
       x = x > carry ? x : carry;
       s_src[i] = x;
-      carry = __shfl(x, kWave - 1);
+      carry = wave_last(x);
     }
     if (lane == 0) s_wmax[w] = carry;
     __syncthreads();
