@@ -240,6 +240,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     s_gbase[d] = a.digit_start[d] + excl;
   }
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets
+  // staged slot i of digit d goes to s_gbase[d] + i from here on
+  for (int d = tid; d < radix; d += NT) s_gbase[d] -= s_toff[d];
 
   // stage keys in sorted order
 #pragma unroll
@@ -263,14 +265,14 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       const uint32_t kv = s_stage[i];
       const uint32_t d = (kv >> a.shift) & dmask;
       dpk[k >> 1] |= d << ((k & 1) * 16);
-      const uint64_t gp = s_gbase[d] + (uint64_t)(i - (int)s_toff[d]);
+      const uint64_t gp = s_gbase[d] + (uint64_t)i;
       if (LAST) a.out_key16[gp] = (uint16_t)(kv & a.fine_mask);
       else a.out_key32[gp] = kv;
     }
   }
   auto gpos_of = [&](int k, int i) -> uint64_t {
     const uint32_t d = (dpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
-    return s_gbase[d] + (uint64_t)(i - (int)s_toff[d]);
+    return s_gbase[d] + (uint64_t)i;
   };
 
   if (LAST) {
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
         const int mid = (lo + hi) >> 1;
         if (fl_of(s_stage[mid]) < fl) lo = mid + 1; else hi = mid;
       }
-      a.bin_start[((uint64_t)d << a.lower_bits) | fl] = s_gbase[d] + (uint64_t)(lo - (int)s_toff[d]);
+      a.bin_start[((uint64_t)d << a.lower_bits) | fl] = s_gbase[d] + (uint64_t)lo;
     }
   }
   __syncthreads();
@@ -568,35 +570,41 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   }
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, fw, s_w32);
-  if (nch == 1) {
-    // a whole bin: its counts are the in-degrees of its vertices
-    for (int v = tid; v < fw; v += NT) {
-      s_cur[v] = bs + s_toff[v];
+  // A whole bin: its counts are the in-degrees of its vertices, and its
+  // staged order is its final CSC order, so staged slot i goes to bs + i.
+  // A chunk of a big bin: slot i of vertex v goes to s_cur[v] + i.
+  const bool whole = nch == 1;
+  for (int v = tid; v < fw; v += NT) {
+    if (whole) {
       if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_toff[v]);
+    } else {
+      s_cur[v] -= s_toff[v];
     }
-    __syncthreads();
   }
   if (cnt == 0) return;
   // the local sorted position of every edge of this thread
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
     if (row_idx(j) < cnt) lpos[j] += s_toff[key[j]] + s_wcnt[w][key[j]];
-  // stage the destination of every sorted slot, then the sources
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (row_idx(j) < cnt) s_stage[lpos[j]] = key[j];
-  __syncthreads();
   uint32_t vpk[(ITEMS + 1) / 2];
 #pragma unroll
   for (int k = 0; k < (ITEMS + 1) / 2; ++k) vpk[k] = 0u;
+  if (!whole) {
+    // the vertex of every sorted slot (for its cursor)
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int i = k * NT + tid;
-    if (i < cnt) vpk[k >> 1] |= s_stage[i] << ((k & 1) * 16);
+    for (int j = 0; j < ITEMS; ++j)
+      if (row_idx(j) < cnt) s_stage[lpos[j]] = key[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int i = k * NT + tid;
+      if (i < cnt) vpk[k >> 1] |= s_stage[i] << ((k & 1) * 16);
+    }
   }
   auto gpos_of = [&](int k, int i) -> uint64_t {
+    if (whole) return bs + (uint64_t)i;
     const uint32_t v = (vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
-    return s_cur[v] + (uint64_t)(i - (int)s_toff[v]);
+    return s_cur[v] + (uint64_t)i;
   };
   {
     uint32_t src[ITEMS];
