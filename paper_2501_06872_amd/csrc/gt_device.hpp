@@ -31,6 +31,9 @@ __device__ __forceinline__ uint64_t match_peers(uint32_t key, uint64_t active) {
 // before the lowest such lane advances it) plus the number of lower lanes
 // with the key; the lowest lane then advances the count and clears the slot.
 // LDS instructions of one wave execute in order, so no barrier is needed.
+// PIN: compute the rank at this point (keeps register pressure low in
+// callers that rank many rows while holding other per-row state).
+template <bool PIN = false>
 __device__ __forceinline__ uint32_t rank_row_lds(uint32_t key, bool ok, uint16_t *wcnt,
                                                  unsigned long long *tab, int lane) {
   const unsigned long long bit = 1ull << lane, lt = bit - 1ull;
@@ -44,7 +47,11 @@ __device__ __forceinline__ uint32_t rank_row_lds(uint32_t key, bool ok, uint16_t
     tab[key] = 0ull;
   }
   __builtin_amdgcn_wave_barrier();
-  return old + (uint32_t)__popcll(peers & lt);
+  uint32_t rank = old + (uint32_t)__popcll(peers & lt);
+  // materialise the rank here: otherwise the compiler may defer this sum
+  // past the caller's unrolled rows and keep every row's 64-bit mask live
+  if (PIN) asm volatile("" : "+v"(rank));
+  return rank;
 }
 
 // Inclusive running maximum across the 64 lanes with DPP moves only (no
@@ -73,6 +80,17 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
 __device__ __forceinline__ uint32_t wave_last(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
+
+// N values below 2^16 held two per 32-bit register (indices known at
+// compile time after unrolling).
+template <int N>
+struct Packed16 {
+  uint32_t w[(N + 1) / 2];
+  __device__ __forceinline__ uint32_t get(int j) const { return (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu; }
+  __device__ __forceinline__ void set(int j, uint32_t v) {
+    w[j >> 1] = (j & 1) ? ((w[j >> 1] & 0xFFFFu) | (v << 16)) : ((w[j >> 1] & 0xFFFF0000u) | v);
+  }
+};
 
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, int lane) {
 #pragma unroll
@@ -162,16 +180,23 @@ __device__ __forceinline__ void status_store(W *p, W v) {
 // already inclusive); a longer chain is then read kLookWin tiles per round
 // trip.
 constexpr int kLookWin = 8;
+
+// First half: publish this tile's aggregate (tile 0: its inclusive prefix).
 template <typename W>
-__device__ __forceinline__ uint64_t lookback_exclusive(W *status, int64_t tile, int64_t stride, int64_t col,
-                                                      uint64_t count) {
+__device__ __forceinline__ void lookback_publish(W *status, int64_t tile, int64_t stride, int64_t col,
+                                                 uint64_t count) {
   using S = Status<W>;
+  status_store(status + tile * stride + col, tile == 0 ? S::incl(count) : S::agg(count));
+}
+
+// Second half: wait for the predecessors, return the exclusive prefix and
+// publish the inclusive one.
+template <typename W>
+__device__ __forceinline__ uint64_t lookback_wait(W *status, int64_t tile, int64_t stride, int64_t col,
+                                                 uint64_t count) {
+  using S = Status<W>;
+  if (tile == 0) return 0;
   W *mine = status + tile * stride + col;
-  if (tile == 0) {
-    status_store(mine, S::incl(count));
-    return 0;
-  }
-  status_store(mine, S::agg(count));
   uint64_t excl = 0;
   int64_t t = tile - 1;
   {
@@ -209,6 +234,13 @@ __device__ __forceinline__ uint64_t lookback_exclusive(W *status, int64_t tile, 
   }
   status_store(mine, S::incl(excl + count));
   return excl;
+}
+
+template <typename W>
+__device__ __forceinline__ uint64_t lookback_exclusive(W *status, int64_t tile, int64_t stride, int64_t col,
+                                                      uint64_t count) {
+  lookback_publish(status, tile, stride, col, count);
+  return lookback_wait(status, tile, stride, col, count);
 }
 
 }  // namespace gt

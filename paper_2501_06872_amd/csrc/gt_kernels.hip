@@ -212,16 +212,18 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   }
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
-  uint32_t lpos[ITEMS];
+  // Local positions stay below the tile size: two per register.
+  Packed16<ITEMS> lpos;
   {
     unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * RADIX;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      lpos[j] = rank_row_lds((key[j] >> a.shift) & dmask, row_idx(j) < cnt, s_wcnt[w], tab, lane);
+      lpos.set(j, rank_row_lds<true>((key[j] >> a.shift) & dmask, row_idx(j) < cnt, s_wcnt[w], tab, lane));
   }
   __syncthreads();
 
-  // per digit: tile total, and exclusive prefix over waves (in place)
+  // per digit: tile total, and exclusive prefix over waves (in place); the
+  // tile's aggregate is published at once so that later tiles can use it
   for (int d = tid; d < radix; d += NT) {
     uint32_t run = 0;
 #pragma unroll
@@ -232,25 +234,25 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     }
     s_tot[d] = run;
     s_toff[d] = run;
+    lookback_publish<SW>(static_cast<SW *>(a.status), tile, radix, d, run);
   }
-  __syncthreads();
-  // look-back per digit across tiles
-  for (int d = tid; d < radix; d += NT) {
-    const uint64_t excl = lookback_exclusive<SW>(static_cast<SW *>(a.status), tile, radix, d, s_tot[d]);
-    s_gbase[d] = a.digit_start[d] + excl;
-  }
-  block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets
-  // staged slot i of digit d goes to s_gbase[d] + i from here on
-  for (int d = tid; d < radix; d += NT) s_gbase[d] -= s_toff[d];
+  block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets (ends with a barrier)
 
-  // stage keys in sorted order
+  // stage keys in sorted order (the keys leave registers before the wait)
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (row_idx(j) < cnt) {
       const uint32_t d = (key[j] >> a.shift) & dmask;
-      lpos[j] += s_toff[d] + s_wcnt[w][d];
-      s_stage[lpos[j]] = key[j];
+      const uint32_t p = lpos.get(j) + s_toff[d] + s_wcnt[w][d];
+      lpos.set(j, p);
+      s_stage[p] = key[j];
     }
+  }
+  // look-back per digit across tiles; staged slot i of digit d goes to
+  // s_gbase[d] + i
+  for (int d = tid; d < radix; d += NT) {
+    const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), tile, radix, d, s_tot[d]);
+    s_gbase[d] = a.digit_start[d] + excl - s_toff[d];
   }
   __syncthreads();
 
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
+      if (row_idx(j) < cnt) s_stage[lpos.get(j)] = src[j];
   }
   __syncthreads();
 #pragma unroll
@@ -356,7 +358,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos[j]] = pay[j];
+      if (row_idx(j) < cnt) s_stage[lpos.get(j)] = pay[j];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
