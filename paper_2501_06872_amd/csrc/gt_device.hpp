@@ -10,20 +10,6 @@ constexpr int kWave = 64;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
-// Lanes of the wave whose `key` equals this lane's key, among `active` lanes.
-// One ballot per key bit; keys must be < 2^BITS.
-template <int BITS>
-__device__ __forceinline__ uint64_t match_peers(uint32_t key, uint64_t active) {
-  uint64_t peers = active;
-#pragma unroll
-  for (int b = 0; b < BITS; ++b) {
-    const bool bit = (key >> b) & 1u;
-    const uint64_t ones = __ballot(bit);
-    peers &= bit ? ones : ~ones;
-  }
-  return peers;
-}
-
 // Stable in-wave ranking of one row of keys (< 2^bits) through LDS.
 // Each lane ORs its lane bit into tab[key] (a per-wave table of 64-bit lane
 // masks, zero between rows), so reading tab[key] back yields the lanes holding

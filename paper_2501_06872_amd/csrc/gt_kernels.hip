@@ -11,16 +11,19 @@
 //              totals -> start of every digit in the partitioned stream.
 //  k_lsd       Step 3, part 1.  Stable partition of the edge stream by one
 //              destination digit (least significant digit first), tile by
-//              tile: coalesced loads, in-wave stable ranking by ballot
-//              matching, per-wave LDS counters, decoupled look-back across
-//              tiles for the per-digit prefix, LDS-staged coalesced writes.
-//              The first pass reads the CSR and derives each edge's source
-//              from the offsets slice staged in LDS; the last pass also
-//              records where every fine vertex bin starts.
+//              tile: coalesced loads, in-wave stable ranking through an LDS
+//              table of lane masks, per-wave LDS counters, decoupled
+//              look-back across tiles for the per-digit prefix, LDS-staged
+//              coalesced writes.  The first pass reads the CSR and derives
+//              each edge's source from the offsets of the tile (marks in LDS,
+//              running maximum across lanes); the last pass also records
+//              where every fine vertex bin starts.
 //  k_final     Step 3, part 2.  One workgroup per bin of 2^fine_bits
-//              destinations: per-vertex in-degrees counted in LDS, exclusive
-//              scan -> CSC offsets of the bin, stable placement of the bin's
-//              edges (ascending source) through LDS, coalesced write-out.
+//              destinations (or per tile-sized chunk of a longer bin, whose
+//              per-chunk counts k_big_count / k_big_scan turn into cursors):
+//              per-vertex in-degrees counted in LDS, exclusive scan -> CSC
+//              offsets of the bin, stable placement of the bin's edges
+//              (ascending source) through LDS, coalesced write-out.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -427,22 +430,6 @@ __global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, int64
   const uint32_t b = item_base[f], c = nch[f];
   for (uint32_t k = 0; k < c; ++k) item_bin[b + k] = (uint32_t)f;
   if (c > 1) bigbins[atomicAdd(nbig, 1u)] = (uint32_t)f;
-}
-
-// In-wave stable ranking of one row of keys (< 2^BITS) against per-wave LDS
-// counters; returns the rank of this lane's key within the wave's stream.
-template <int BITS>
-__device__ __forceinline__ uint32_t rank_row(uint32_t key, bool ok, uint16_t *wcnt, uint64_t ltmask, int lane) {
-  const uint64_t active = __ballot(ok);
-  const uint64_t peers = match_peers<BITS>(key, active);
-  const int leader = peers ? (__ffsll((unsigned long long)peers) - 1) : lane;
-  uint32_t old = 0;
-  if (ok && lane == leader) {
-    old = wcnt[key];
-    wcnt[key] = (uint16_t)(old + __popcll(peers));
-  }
-  old = __shfl(old, leader);
-  return old + __popcll(peers & ltmask);
 }
 
 // Big bins: in-degree of every vertex of the bin within each chunk.
