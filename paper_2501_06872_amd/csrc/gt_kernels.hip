@@ -125,7 +125,15 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int
   const int64_t nvec = m >> 2;
   const uint4 *D4 = reinterpret_cast<const uint4 *>(D);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid; i < nvec; i += stride) count4(D4[i]);
+  int64_t i0 = blockIdx.x * (int64_t)blockDim.x + tid;
+  for (; i0 + 3 * stride < nvec; i0 += 4 * stride) {  // four loads in flight per thread
+    const uint4 q0 = D4[i0], q1 = D4[i0 + stride], q2 = D4[i0 + 2 * stride], q3 = D4[i0 + 3 * stride];
+    count4(q0);
+    count4(q1);
+    count4(q2);
+    count4(q3);
+  }
+  for (; i0 < nvec; i0 += stride) count4(D4[i0]);
   for (int64_t i = (nvec << 2) + blockIdx.x * (int64_t)blockDim.x + tid; i < m; i += stride) count((uint32_t)D[i]);
   if (bad) atomicOr(err, kErrBadIndex);
   __syncthreads();
@@ -206,12 +214,26 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   // rows of 64 consecutive edges; wave w owns rows [w*ITEMS, (w+1)*ITEMS)
   auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
 
-  // Keys only; sources and payload are loaded when they are staged.
+  // Keys, and (later passes) the sources and payload with them, so that
+  // their latency hides behind the ranking and the look-back.  The first
+  // pass derives its sources from the offsets further down.
   uint32_t key[ITEMS];
+  uint32_t src_in[CSR_IN ? 1 : ITEMS];
+  uint32_t pay_in[PAY ? ITEMS : 1];
   {
     const uint32_t *kin = CSR_IN ? reinterpret_cast<const uint32_t *>(a.D) + base : a.in_key + base;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? kin[row_idx(j)] : 0u;
+    if constexpr (!CSR_IN) {
+      const int32_t *sin = a.in_src + base;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) src_in[j] = row_idx(j) < cnt ? (uint32_t)sin[row_idx(j)] : 0u;
+    }
+    if constexpr (PAY) {
+      const uint32_t *pin = CSR_IN ? a.P + base : a.in_pay + base;
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) pay_in[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
+    }
   }
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
@@ -339,9 +361,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) src[j] = src[j] > before ? src[j] : before;
     } else {
-      const int32_t *sin = a.in_src + base;
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)sin[row_idx(j)] : 0u;
+      for (int j = 0; j < ITEMS; ++j) src[j] = src_in[CSR_IN ? 0 : j];
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
@@ -354,14 +375,10 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     if (i < cnt) a.out_src[gpos_of(k, i)] = (int32_t)s_stage[i];
   }
   if (PAY) {
-    uint32_t pay[ITEMS];
-    const uint32_t *pin = CSR_IN ? a.P + base : a.in_pay + base;
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) pay[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos.get(j)] = pay[j];
+      if (row_idx(j) < cnt) s_stage[lpos.get(j)] = pay_in[PAY ? j : 0];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -535,8 +552,13 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   }
   __syncthreads();
   uint32_t key[ITEMS], lpos[ITEMS];
+  // keys and sources at once (the sources are staged later; the payload is
+  // loaded when it is staged, which keeps three workgroups per CU)
+  uint32_t src[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? (uint32_t)(a.in_key[cb + row_idx(j)] & vmask) : 0u;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)a.in_src[cb + row_idx(j)] : 0u;
   {
     unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FW;
 #pragma unroll
@@ -595,15 +617,10 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
     const uint32_t v = (vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
     return s_cur[v] + (uint64_t)i;
   };
-  {
-    uint32_t src[ITEMS];
+  __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)a.in_src[cb + row_idx(j)] : 0u;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
-  }
+  for (int j = 0; j < ITEMS; ++j)
+    if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
