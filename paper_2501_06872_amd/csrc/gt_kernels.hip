@@ -235,6 +235,14 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       for (int j = 0; j < ITEMS; ++j) pay_in[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
     }
   }
+  // first pass: the source of the tile's first edge and the first offset
+  // each thread inspects for the source marks, also loaded up front
+  int64_t u0 = 0, o_first = 0;
+  if constexpr (CSR_IN) {
+    u0 = a.tile_src0[tile];
+    const int64_t u = u0 + 1 + tid;
+    o_first = u < a.n ? a.O[u] : a.m;
+  }
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
   // Local positions stay below the tile size: two per register.
@@ -336,12 +344,13 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       // fill forward (sources increase along the edge array)
       lds_zero16(s_stage, TILE * 4, tid, NT);
       __syncthreads();
-      const int64_t u0 = a.tile_src0[tile];
       if (tid == 0) s_stage[0] = (uint32_t)u0;
-      for (int64_t u = u0 + 1 + tid; u < a.n; u += NT) {
-        const int64_t o = a.O[u];
+      int64_t o = o_first;
+      for (int64_t u = u0 + 1 + tid; u < a.n;) {
         if (o >= base + cnt64) break;
         if (o > base) atomicMax(&s_stage[o - base], (uint32_t)u);
+        u += NT;
+        if (u < a.n) o = a.O[u];
       }
       __syncthreads();
       // running maximum along the wave's rows, kept in registers (each
