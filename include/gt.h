@@ -81,8 +81,7 @@ enum {
 typedef struct {
   int32_t policy;        /* GT_POLICY_* */
   int32_t fine_bits;     /* log2 of the vertex range sorted in LDS by the last kernel (4..9) */
-  int32_t digit_bits;    /* maximum digit width of one stable partition pass (4..10; widths
-                            above 9 are clamped to 9) */
+  int32_t digit_bits;    /* maximum digit width of one stable partition pass (4..10) */
   int32_t variant;       /* tile variant of the partition kernels (0 = auto, 1..N) */
   int32_t validate;      /* 1: check offsets/indices on the device (status word) */
   uint64_t seed;         /* seed of the degree-sampling pass */

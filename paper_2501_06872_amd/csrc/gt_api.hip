@@ -77,10 +77,10 @@ void finalize_params(GraphPlan &p, size_t base) {
   fb = std::min(fb, L - 1);
   fb = std::max(fb, 0);
   p.fine_bits = fb;
-  if (L - fb > kMaxPasses * kMaxDigitBits) fb = L - kMaxPasses * kMaxDigitBits;  // at most 3 digits
+  if (L - fb > kMaxPasses * 10) fb = L - kMaxPasses * 10;  // at most 3 digits of <= 10 bits
   p.fine_bits = fb;
   const int dbits = L - fb;  // >= 1
-  int maxb = std::max(1, std::min(p.digit_bits, kMaxDigitBits));
+  int maxb = std::max(1, std::min(p.digit_bits, 10));
   maxb = std::max(maxb, (dbits + kMaxPasses - 1) / kMaxPasses);  // widen digits rather than add passes
   p.passes = (dbits + maxb - 1) / maxb;
   int rem = dbits, shift = fb, maxbits = 0;
@@ -94,9 +94,10 @@ void finalize_params(GraphPlan &p, size_t base) {
   }
   p.max_bits = maxbits;
   p.total_bits = dbits;
-  // Every pass of a plan runs one tile variant, so that one tile size holds
-  // for the tile sources, the look-back status words and every pass's grid
-  // (a variant without an instance for the widest digit maps to variant 1).
+  // The 16-wave tiles have no 10-bit instance (their lane-mask tables would
+  // not fit LDS): such plans use the 8-wave x 16-edge tile for every pass, so
+  // that one tile size holds for the tile sources, the look-back status
+  // words and every pass's grid.
   p.variant = lsd_variant_for(p.variant, maxbits);
   p.nbins_total = int64_t(1) << dbits;
   p.nbins = (p.n + (int64_t(1) << fb) - 1) >> fb;

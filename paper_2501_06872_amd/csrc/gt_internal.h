@@ -6,11 +6,7 @@
 namespace gt {
 
 constexpr int kMaxPasses = 3;
-// Digits of at most 9 bits: the 10-bit instances of the partition kernel
-// were withdrawn after two unexplained memory faults (first pass, no
-// payload); wider requests are clamped, using one more pass where needed.
-constexpr int kMaxDigitBits = 9;
-constexpr int kMaxRadix = 1 << kMaxDigitBits;
+constexpr int kMaxRadix = 1024;   // digit width <= 10 bits
 constexpr int kMaxFineBits = 9;   // bins of <= 512 destinations in k_final
 constexpr int kHistBlocks = 1280;
 

@@ -701,11 +701,12 @@ int lsd_variant_for(int variant, int max_bits) {
 hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide,
                       hipStream_t st) {
   if (a.m <= 0) return hipSuccess;
-  if (rbits < 1 || rbits > kMaxDigitBits || lsd_variant_for(variant, rbits) != variant) return hipErrorInvalidValue;
-  const int rb = rbits <= 8 ? 8 : 9;
+  if (rbits < 1 || rbits > 10 || lsd_variant_for(variant, rbits) != variant) return hipErrorInvalidValue;
+  const int rb = rbits <= 8 ? 8 : (rbits <= 9 ? 9 : 10);
 #define GT_V(W, I)                                                                       \
   return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, wide, st)                      \
-                 : launch_lsd_t<W, I, 9>(a, csr_in, pay, last, wide, st)
+                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, wide, st)           \
+                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, wide, st))
   switch (variant) {
     case 2:  // 16 waves x 8 edges, digits of up to 9 bits
       return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, wide, st)

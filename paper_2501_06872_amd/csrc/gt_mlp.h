@@ -15,11 +15,11 @@ size_t mlp_work_floats(int batch);
 hipError_t mlp_forward(const float *params, const float *x, int batch, float *y, hipStream_t st);
 
 // Configuration c of the learned/autotuned choice:
-// fine_bits = 6 + c / 8, variant = 1 + (c / 2) % 4, digit_bits = (c % 2) ? 9 : 8.
+// fine_bits = 6 + c / 8, variant = 1 + (c / 2) % 4, digit_bits = (c % 2) ? 10 : 8.
 inline void config_params(int c, int *fine_bits, int *digit_bits, int *variant) {
   *fine_bits = 6 + c / 8;
   *variant = 1 + (c / 2) % 4;
-  *digit_bits = (c % 2) ? 9 : 8;
+  *digit_bits = (c % 2) ? 10 : 8;
 }
 
 }  // namespace gt

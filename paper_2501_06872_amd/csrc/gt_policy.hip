@@ -29,7 +29,7 @@ size_t plan_scratch_bytes(const gt_csr_t *graphs, int32_t count) {
 }
 
 // Heuristic: a k_final bin should hold about one 8K-edge tile, so
-// fine_bits ~ log2(8192 / average in-degree); digits as wide as allowed; the
+// fine_bits ~ log2(8192 / average in-degree); digits of up to 10 bits; the
 // 8-wave x 16-edge tile.
 static void heuristic(GraphPlan &p) {
   const double avg = p.n > 0 ? (double)p.m / (double)p.n : 1.0;

@@ -57,7 +57,7 @@ def heuristic_config(n, m):
     avg = m / max(n, 1)
     fb = int(round(math.log2(8192.0 / max(avg, 1.0))))
     fb = min(max(fb, 6), 9)
-    return (fb - 6) * 8 + 0 * 2 + 1  # variant 1, the widest digits
+    return (fb - 6) * 8 + 0 * 2 + 1  # variant 1, 10-bit digits
 
 
 def collect(specs, dev, reps, seed=77, verbose=False):

@@ -142,7 +142,7 @@ def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
 
 @pytest.mark.parametrize("fine_bits,digit_bits,variant", [
     (1, 4, 1), (4, 6, 3), (8, 10, 2), (9, 4, 1), (5, 10, 3), (7, 8, 2), (9, 10, 1), (6, 5, 1), (8, 9, 4), (3, 6, 4),
-    (7, 10, 4), (7, 10, 2),  # 10 coarse bits: a requested width of 10 becomes two passes of 5
+    (7, 10, 4), (7, 10, 2),  # one 10-bit pass: the 16-wave variants run the 8-wave tile
 ])
 def test_parameter_sweep_same_output(hip_device, fine_bits, digit_bits, variant):
     # 1, 2 and 3 partition passes, every tile variant, narrow and wide bins

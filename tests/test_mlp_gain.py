@@ -23,7 +23,7 @@ MODELS = os.path.join(ROOT, "paper_2501_06872_amd", "models")
 
 def heuristic_config(n, m):
     # the library's heuristic: fine_bits = round(log2(8192 / average in-degree)),
-    # the widest digits (9 bits), tile variant 1; its index in the grid c = (fb-6)*8 + 1
+    # 10-bit digits, tile variant 1; its index in the grid c = (fb-6)*8 + ...
     fb = int(round(math.log2(8192.0 / max(m / max(n, 1), 1.0))))
     fb = min(max(fb, 6), 9)
     return (fb - 6) * 8 + 1
@@ -57,7 +57,7 @@ def choices(p, fmin, fmax, X, sizes):
 def test_heuristic_index_matches_the_grid():
     import paper_2501_06872_amd as gt
     c = heuristic_config(1 << 20, 16 << 20)  # average degree 16 -> fine_bits 9
-    assert gt.config(c) == dict(fine_bits=9, digit_bits=9, variant=1)
+    assert gt.config(c) == dict(fine_bits=9, digit_bits=10, variant=1)
 
 
 def test_trained_network_beats_the_heuristic_on_held_out_graphs(stored):
