@@ -234,10 +234,6 @@ def main():
         sys.exit(2)
     if args.workload == "batch512":
         return bench_batch(args)
-    if args.workload == "rmat28p":
-        print("rmat28p (2^32 edges) is refused by this build: graphs of 2^31 edges or more are not supported",
-              file=sys.stderr)
-        sys.exit(2)
 
     import torch
     import gen

@@ -13,8 +13,7 @@
  *
  * Types and layout (all arrays are device memory, owned by the caller):
  *   offsets  int64[n+1]   offsets[0] = 0, nondecreasing, offsets[n] = m
- *   indices  int32[m]     0 <= indices[e] < n;  n <= 2^31 - 1;  m < 2^31 (larger
- *                         graphs are refused by gt_plan with GT_ERR_UNSUPPORTED)
+ *   indices  int32[m]     0 <= indices[e] < n;  n <= 2^31 - 1
  *   payload  uint32[m]    optional; 32-bit words copied bit-exactly (a float
  *                         payload is passed as its bit pattern)
  * Output arrays (caller-allocated, must not alias the input):
@@ -51,7 +50,7 @@ typedef enum {
   GT_ERR_INVALID_ARGUMENT = 1,   /* NULL pointer, negative size, n > 2^31-1, payload mismatch */
   GT_ERR_INVALID_GRAPH = 2,      /* device-detected: bad offsets or an index outside [0, n) */
   GT_ERR_WORKSPACE_TOO_SMALL = 3,
-  GT_ERR_UNSUPPORTED = 4,        /* a parameter outside the compiled kernel variants, or m >= 2^31 */
+  GT_ERR_UNSUPPORTED = 4,        /* a parameter outside the compiled kernel variants */
   GT_ERR_HIP = 5                 /* a HIP runtime call failed */
 } gt_status;
 

@@ -20,7 +20,6 @@ using namespace gt;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kMaxEdgesSupported = int64_t(1) << 31;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int ceil_log2(int64_t x) {
@@ -390,12 +389,6 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_MLP) return GT_ERR_INVALID_ARGUMENT;
   if (o.strategy < GT_STRATEGY_STABLE || o.strategy > GT_STRATEGY_ATOMIC || o.hdv_max < 0 || o.hdv_max > kHlhMaxHdv)
     return GT_ERR_UNSUPPORTED;
-  // Graphs of 2^31 edges or more are refused: their first run (2^32 edges,
-  // 64-bit look-back words, 10-bit digits) ended in a memory fault whose
-  // cause is not established; the 64-bit look-back itself stays testable on
-  // small graphs through GT_FLAG_WIDE_STATUS.
-  for (int32_t i = 0; i < count; ++i)
-    if (graphs[i].m >= kMaxEdgesSupported) return GT_ERR_UNSUPPORTED;
   if (o.policy == GT_POLICY_FIXED) {
     if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
         (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 4)

@@ -269,6 +269,9 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     s_toff[d] = run;
     lookback_publish<SW>(static_cast<SW *>(a.status), tile, radix, d, run);
   }
+  // the scan below reads s_toff in blocks of radix / NT entries per thread,
+  // so with more digits than threads it reads other threads' writes
+  __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets (ends with a barrier)
 
   // stage keys in sorted order (the keys leave registers before the wait)

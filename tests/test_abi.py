@@ -82,17 +82,3 @@ def test_every_config_plans_a_tile_variant_that_has_an_instance():
                 assert pv == v, (n, c, pdb, pv)
             assert L.gt_plan_destroy(h) == gt.GT_OK
     assert seen_fallback
-
-
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libgt.so not built")
-def test_graphs_of_2_31_edges_or_more_are_refused():
-    import paper_2501_06872_amd as gt
-    L = gt.lib()
-    h = ctypes.c_void_p()
-    for m, want in (((1 << 31) - 1, gt.GT_OK), (1 << 31, gt.GT_ERR_UNSUPPORTED), (1 << 32, gt.GT_ERR_UNSUPPORTED)):
-        g = gt.CSR(1 << 26, m, 1, 1, None)
-        opts = gt.make_options(policy=gt.POLICY_FIXED, fine_bits=9, digit_bits=10, variant=1)
-        rc = L.gt_plan(ctypes.byref(g), 1, ctypes.byref(opts), None, 0, None, ctypes.byref(h))
-        assert rc == want, (m, rc)
-        if rc == gt.GT_OK:
-            L.gt_plan_destroy(h)

@@ -152,6 +152,22 @@ def test_parameter_sweep_same_output(hip_device, fine_bits, digit_bits, variant)
     say("params", params)
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_ten_bit_first_pass_without_payload(hip_device, flags):
+    # 1024 digits with 512 threads: the tile-local digit scan reads entries
+    # that other waves write (needs the barrier before it); one 10-bit pass,
+    # then a 10-bit first pass of two, 32- and 64-bit look-back words
+    O, D, P = gen.rmat(17, 16, seed=13, permute=False)
+    assert_parity(O, D, P, hip_device, "rmat17 one 10-bit pass", policy=1, fine_bits=7, digit_bits=10, variant=1,
+                  flags=flags)
+    O, D, P = gen.uniform(1 << 20, 4, seed=14)
+    assert_parity(O, D, P, hip_device, "uniform20 10+9-bit passes", policy=1, fine_bits=1, digit_bits=10, variant=1,
+                  flags=flags)
+    O, D, P = gen.rmat(19, 8, seed=15, permute=False, payload=True)
+    assert_parity(O, D, P, hip_device, "rmat19 payload 10-bit", policy=1, fine_bits=9, digit_bits=10, variant=3,
+                  flags=flags)
+
+
 @pytest.mark.parametrize("payload", [False, True])
 def test_wide_lookback_words(hip_device, payload):
     # the 64-bit look-back words of graphs with m >= 2^31, forced on a small graph
