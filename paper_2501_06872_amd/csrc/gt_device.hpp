@@ -97,7 +97,10 @@ __device__ __forceinline__ uint64_t wave_incl_sum64(uint64_t v, int lane) {
 }
 
 // Exclusive prefix sum of s[0..len) in LDS, in place; returns the total.
-// NT threads; len <= 4 * NT.  `wsum` is scratch of NT/64 entries.
+// NT threads; len <= 4 * NT.  `wsum` is scratch of NT/64 + 1 entries.
+// Thread t starts by reading s[t*per .. (t+1)*per) with per = ceil(len/NT),
+// entries other threads may have written: callers put a barrier between
+// writing s and this call.  Ends with a barrier.
 template <int NT, typename T>
 __device__ T block_excl_scan(T *s, int len, T *wsum) {
   constexpr int NW = NT / kWave;
