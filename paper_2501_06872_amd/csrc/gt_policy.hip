@@ -35,7 +35,12 @@ static void heuristic(GraphPlan &p) {
   const double avg = p.n > 0 ? (double)p.m / (double)p.n : 1.0;
   int fb = (int)lround(log2(8192.0 / std::max(avg, 1.0)));
   p.fine_bits = std::min(std::max(fb, 4), kMaxFineBits);
-  p.digit_bits = 10;
+  // 10-bit digits only for a single pass: with 19 or 20 coarse bits, three
+  // passes of at most 7 bits beat a 10-bit pass (whose 1024 look-back words
+  // per tile and 98 KB of LDS allow one workgroup per CU)
+  int L = 1;
+  while (L < 31 && (int64_t(1) << L) < std::max<int64_t>(p.n, 2)) ++L;
+  p.digit_bits = (L - p.fine_bits > 18) ? 9 : 10;
   p.variant = 1;
 }
 
