@@ -57,7 +57,7 @@ def heuristic_config(n, m):
     avg = m / max(n, 1)
     fb = int(round(math.log2(8192.0 / max(avg, 1.0))))
     fb = min(max(fb, 6), 9)
-    L = max(1, (max(n, 2) - 1).bit_length())
+    L = max(1, (max(int(n), 2) - 1).bit_length())
     # variant 1; 10-bit digits, or 8-bit ones (the same three passes as the
     # heuristic's 9) when the coarse bits would need two 10-bit passes
     return (fb - 6) * 8 + (0 if L - fb > 18 else 1)

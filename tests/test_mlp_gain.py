@@ -26,7 +26,7 @@ def heuristic_config(n, m):
     # 10-bit digits, tile variant 1; its index in the grid c = (fb-6)*8 + ...
     fb = int(round(math.log2(8192.0 / max(m / max(n, 1), 1.0))))
     fb = min(max(fb, 6), 9)
-    L = max(1, (max(n, 2) - 1).bit_length())
+    L = max(1, (max(int(n), 2) - 1).bit_length())
     return (fb - 6) * 8 + (0 if L - fb > 18 else 1)  # 8-bit digits plan the same three passes as 9
 
 
