@@ -122,30 +122,67 @@ gt_status gt_plan_scratch_size(const gt_csr_t *graphs, int32_t count, size_t *by
  * gt_plan_set_config). */
 gt_status gt_plan_workspace_size(gt_plan_t plan, size_t *bytes_out);
 
-/* Build a plan for `count` graphs (count == 1 for gt_transpose).  When the
- * policy needs sampled features the sampling kernels run on `stream` using
- * `workspace`, and the stream is synchronised once. */
+/* Build a plan for `count` graphs (count == 1 for gt_transpose): the
+ * preprocessing of Section IV-C (Step 0: a degree sample of 1% of |V| edge
+ * positions, then the choice of parameters; Eq. 1 sizes the LDS-resident
+ * work of the heuristic).
+ *   graphs      host array of `count` descriptors (device pointers inside,
+ *               read by the sampling kernels during this call only)
+ *   opt         options, or NULL for the defaults
+ *   workspace   device buffer of at least gt_plan_scratch_size() bytes for
+ *               the HEURISTIC and MLP policies (may be NULL for FIXED);
+ *               clobbered
+ *   stream      HIP stream (hipStream_t) of the sampling kernels; the call
+ *               synchronises it once when the policy samples
+ *   plan_out    receives the plan (host memory only; gt_plan_destroy)
+ * Errors: GT_ERR_INVALID_ARGUMENT (NULL pointer, count <= 0, n < 0, m < 0,
+ * n > 2^31 - 1), GT_ERR_UNSUPPORTED (an option out of range),
+ * GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_HIP. */
 gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
                   size_t workspace_bytes, void *stream, gt_plan_t *plan_out);
 
-/* Transpose one graph (the plan was built with count == 1 for a graph of the
- * same n, m and payload presence).  Asynchronous on `stream`. */
+/* Transpose one graph (Section II-A; the result Algorithm 1 reaches when run
+ * by one thread, lists in increasing CSR edge position for the stable
+ * strategy).  The plan was built with count == 1 for a graph of the same n,
+ * m and payload presence.
+ *   g           CSR in device memory (offsets int64[n+1], indices int32[m],
+ *               payload uint32[m] or NULL); not modified
+ *   out         caller-allocated CSC: offsets int64[n+1], indices int32[m],
+ *               payload uint32[m] (NULL iff g->payload is NULL); must not
+ *               alias the input
+ *   workspace   at least gt_plan_workspace_size() bytes; clobbered
+ *   stream      HIP stream; the call only enqueues kernels (no host
+ *               synchronisation, capturable into a HIP graph)
+ * Errors: GT_ERR_INVALID_ARGUMENT (NULL pointers, sizes other than the
+ * plan's), GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_HIP (a launch failed).  With
+ * opt->validate an invalid graph is reported by gt_device_status() after the
+ * stream has completed; without it the output of an invalid graph is
+ * undefined (but every kernel stays inside its buffers). */
 gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *workspace,
                        size_t workspace_bytes, void *stream);
 
-/* Transpose `count` graphs in one batched launch sequence (plan built for the
- * same count and sizes).  Asynchronous on `stream`. */
+/* Transpose `count` graphs (each as gt_transpose) for a plan built for the
+ * same count and sizes.  The kernels of different graphs run on the plan's
+ * internal streams (forked from `stream` by one event and joined back by one
+ * event per stream), so the whole call is one asynchronous, capturable
+ * launch sequence on `stream`.  graphs / outs: host arrays of `count`
+ * descriptors.  Errors as gt_transpose. */
 gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
                                void *workspace, size_t workspace_bytes, void *stream);
 
 /* After the stream has been synchronised: GT_OK, or GT_ERR_INVALID_GRAPH if
- * validation found a bad input.  Reads 4 bytes of the workspace. */
+ * validation found a bad input (offsets not nondecreasing from 0 to m, or an
+ * index outside [0, n)).  Reads 4 bytes of the workspace (device memory). */
 gt_status gt_device_status(const void *workspace);
 
-/* Parameters a plan selected for graph `i` (for reporting and tests). */
+/* Parameters a plan selected for graph `i` (for reporting and tests): fine
+ * bits of the per-bin placement, widest digit, number of partition passes,
+ * tile variant.  Any output pointer may be NULL. */
 gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits,
                          int32_t *passes, int32_t *variant);
 
+/* Release the plan's host memory and internal streams/events.  Work already
+ * enqueued with it is unaffected. */
 gt_status gt_plan_destroy(gt_plan_t plan);
 
 /* Per-kernel timing for measurement.  While enabled, gt_transpose records a
