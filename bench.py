@@ -222,8 +222,9 @@ def main():
     ap.add_argument("--fine-bits", type=int, default=0)
     ap.add_argument("--digit-bits", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
-    ap.add_argument("--strategy", default="stable", choices=["stable", "hlh", "atomic"],
-                    help="hlh / atomic: the paper's unordered methods (list order left to atomics)")
+    ap.add_argument("--strategy", default="stable", choices=["stable", "hlh", "atomic", "probe"],
+                    help="hlh / atomic: the paper's unordered methods (list order left to atomics); "
+                         "probe: the one of the two that counts faster on a sample of the edges")
     ap.add_argument("--check", action="store_true", help="check the output on sampled vertex ranges")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB once before timing (reference for HBM byte counters)")
@@ -249,13 +250,15 @@ def main():
     O_t = torch.from_numpy(O).to(dev)
     D_t = torch.from_numpy(D).to(dev)
     P_t = torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None
-    strategy = {"stable": gt.STRATEGY_STABLE, "hlh": gt.STRATEGY_HLH, "atomic": gt.STRATEGY_ATOMIC}[args.strategy]
+    strategy = {"stable": gt.STRATEGY_STABLE, "hlh": gt.STRATEGY_HLH, "atomic": gt.STRATEGY_ATOMIC,
+                "probe": gt.STRATEGY_PROBE}[args.strategy]
     opts = gt.make_options(strategy=strategy)
     if args.fine_bits or args.digit_bits or args.variant:
         opts = gt.make_options(policy=gt.POLICY_FIXED, fine_bits=args.fine_bits, digit_bits=args.digit_bits,
                                variant=args.variant, strategy=strategy)
     plan = gt.Plan([(O_t, D_t, P_t)], opts)
     params = plan.params()
+    resolved = {gt.STRATEGY_STABLE: "stable", gt.STRATEGY_HLH: "hlh", gt.STRATEGY_ATOMIC: "atomic"}[plan.strategy()]
     out = plan.alloc_out(0, P_t.dtype if P_t is not None else None)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -329,7 +332,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": n, "m": m,
-                   "payload_bytes": w, "strategy": args.strategy,
+                   "payload_bytes": w, "strategy": args.strategy, "strategy_run": resolved,
                    "params": params if args.strategy == "stable" else None},
         "path_hbm_frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "path_alg_bytes": b_alg,

@@ -99,8 +99,17 @@ typedef struct {
  *                      LDS counters; LDVs through wave-aggregated global
  *                      atomics.
  *   GT_STRATEGY_ATOMIC Atomic GT (Algorithm 1): every destination through
- *                      wave-aggregated global atomics. */
-enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2 };
+ *                      wave-aggregated global atomics.
+ *   GT_STRATEGY_PROBE  the probe of Section IV-C: gt_plan times the in-degree
+ *                      count (Step 1) with and without the HDV table on a
+ *                      sixteenth of the edges (the first sixteenth of every
+ *                      edge chunk, on the grid of a full launch) and keeps
+ *                      the faster of HLH and Atomic GT (gt_plan_strategy
+ *                      reports it; an empty graph gets Atomic GT).  gt_plan
+ *                      then needs a workspace of gt_workspace_size() bytes
+ *                      (GT_ERR_WORKSPACE_TOO_SMALL otherwise) and
+ *                      synchronises the stream. */
+enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2, GT_STRATEGY_PROBE = 3 };
 
 /* Flags.  GT_FLAG_WIDE_STATUS forces the 64-bit look-back words that graphs
  * with m >= 2^31 use, so that path can be tested on small graphs. */
@@ -180,6 +189,10 @@ gt_status gt_device_status(const void *workspace);
  * tile variant.  Any output pointer may be NULL. */
 gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits,
                          int32_t *passes, int32_t *variant);
+
+/* The strategy a plan runs for graph `i` (GT_STRATEGY_*; a probed plan
+ * reports the method the probe kept). */
+gt_status gt_plan_strategy(gt_plan_t plan, int32_t i, int32_t *strategy);
 
 /* Release the plan's host memory and internal streams/events.  Work already
  * enqueued with it is unaffected. */

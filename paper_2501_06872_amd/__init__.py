@@ -24,11 +24,12 @@ GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL
 POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
 # STABLE: every CSC list in CSR edge order.  HLH / ATOMIC: the paper's methods,
 # list order left to the atomics (offsets and list contents exact).
-STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC = range(3)
+STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
-           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
+           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_strategy", "gt_plan_destroy",
+           "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
 NUM_FEATURES = 16
@@ -76,6 +77,7 @@ def lib():
         L.gt_transpose_batched.argtypes = [vp, i32, P(CSR), P(CSC), vp, sz, vp]
         L.gt_device_status.argtypes = [vp]
         L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
+        L.gt_plan_strategy.argtypes = [vp, i32, P(i32)]
         L.gt_plan_destroy.argtypes = [vp]
         L.gt_profile.argtypes = [vp, i32]
         L.gt_profile_read.argtypes = [vp, i32, vp, vp, vp, P(i32)]
@@ -157,11 +159,14 @@ class Plan:
         self._shapes = [(g[0].numel() - 1, g[1].numel(), g[2] is not None) for g in graphs]
         # planning needs the sampling scratch only; the transposition needs
         # what the chosen parameters need (gt_plan_workspace_size)
+        opts = options if options is not None else make_options()
         ws = ctypes.c_size_t(0)
-        _check(L.gt_plan_scratch_size(arr, self.count, ctypes.byref(ws)), "gt_plan_scratch_size")
+        if opts.strategy == STRATEGY_PROBE:  # the probe runs Step 1 in the transposition layout
+            _check(L.gt_workspace_size(arr, self.count, ctypes.byref(ws)), "gt_workspace_size")
+        else:
+            _check(L.gt_plan_scratch_size(arr, self.count, ctypes.byref(ws)), "gt_plan_scratch_size")
         self.workspace = self._buffer(int(ws.value), workspace)
         h = ctypes.c_void_p()
-        opts = options if options is not None else make_options()
         _check(L.gt_plan(arr, self.count, ctypes.byref(opts), self.workspace.data_ptr(), self.workspace.numel(),
                          _stream_ptr(self.device), ctypes.byref(h)), "gt_plan")
         self.handle = h
@@ -190,6 +195,11 @@ class Plan:
         _check(lib().gt_plan_params(self.handle, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                     ctypes.byref(d)), "gt_plan_params")
         return dict(fine_bits=a.value, digit_bits=b.value, passes=c.value, variant=d.value)
+
+    def strategy(self, i=0):
+        out = ctypes.c_int32()
+        _check(lib().gt_plan_strategy(self.handle, i, ctypes.byref(out)), "gt_plan_strategy")
+        return out.value
 
     def alloc_out(self, i=0, payload_dtype=torch.uint32):
         n, m, pay = self._shapes[i]

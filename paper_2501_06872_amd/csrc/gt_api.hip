@@ -284,38 +284,90 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
 }
 
 // The unordered strategies (Atomic GT and HLH): count, aggregate, scatter.
-gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
-                            hipStream_t st) {
-  hipError_t e = hipSuccess;
-#define GT_CHK(x) do { e = (x); if (e != hipSuccess) return GT_ERR_HIP; } while (0)
-#define GT_TIMED(name, x) do { if (prof) GT_CHK(prof->begin(name, st)); GT_CHK(x); if (prof) GT_CHK(prof->end(st)); } while (0)
+static UnorderedArgs unordered_args(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t *out, char *ws) {
   UnorderedArgs u{};
   u.O = g.offsets; u.D = g.indices; u.P = g.payload;
   u.n = p.n; u.m = p.m;
-  u.chunk = p.chunk; u.nchunks = p.nchunks;
+  u.chunk = p.chunk; u.nchunks = p.nchunks; u.span = p.chunk;
   u.kmax = p.kmax;
   u.log2slots = kHlhLog2Slots;
   u.hdv = reinterpret_cast<const int32_t *>(ws + p.off_u_hdv);
   u.cnt = reinterpret_cast<uint32_t *>(ws + p.off_u_cnt);
   u.H = reinterpret_cast<uint32_t *>(ws + p.off_u_H);
-  u.T = out.offsets; u.S = out.indices; u.Q = out.payload;
+  if (out) { u.T = out->offsets; u.S = out->indices; u.Q = out->payload; }
   u.cur = reinterpret_cast<unsigned long long *>(ws + p.off_u_cur);
   u.err = reinterpret_cast<uint32_t *>(ws);
   u.scan_status = reinterpret_cast<uint64_t *>(ws + p.off_u_sstatus);
   u.scan_ticket = reinterpret_cast<uint32_t *>(ws + p.off_u_ticket);
+  return u;
+}
+
+// Step 0 of HLH: the degree sample and the HDV list (at most kmax vertices).
+static hipError_t enqueue_hdv_list(const GraphPlan &p, const gt_csr_t &g, char *ws, Profiler *prof, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  SampleArgs sa{};
+  float *feat = nullptr;
+  if (prof && (e = prof->begin("k_sample", st)) != hipSuccess) return e;
+  if ((e = enqueue_sampling(g.offsets, g.indices, p.n, p.m, p.pay, p.seed, ws + p.off_u_samp, &feat, st, &sa)) !=
+      hipSuccess)
+    return e;
+  if (prof && (e = prof->end(st)) != hipSuccess) return e;
+  if (prof && (e = prof->begin("k_hdv_select", st)) != hipSuccess) return e;
+  if ((e = launch_hdv_select(sa.keys, sa.counts, sa.mask, p.kmax, reinterpret_cast<uint32_t *>(ws + p.off_u_hist),
+                             reinterpret_cast<uint32_t *>(ws + p.off_u_thr),
+                             reinterpret_cast<int32_t *>(ws + p.off_u_hdv),
+                             reinterpret_cast<uint32_t *>(ws + p.off_u_nhdv), st)) != hipSuccess)
+    return e;
+  if (prof && (e = prof->end(st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// The probe of Section IV-C: Step 1 (the in-degree count) timed with the HDV
+// table and without it (Atomic GT) on a sixteenth of the edges, the first
+// sixteenth of every chunk, so that the sample spans the whole edge array and
+// runs on the grid of a full launch; the plan keeps the faster.  Runs in `ws`
+// (the layout of an HLH plan at offset kAlign) and synchronises `st`.
+gt_status probe_strategy(GraphPlan &p, const gt_csr_t &g, char *ws, size_t ws_bytes, hipStream_t st) {
+  if (p.n == 0 || p.m == 0) { p.strategy = GT_STRATEGY_ATOMIC; return GT_OK; }
+  GraphPlan q = p;
+  q.strategy = GT_STRATEGY_HLH;
+  if (ws == nullptr || unordered_workspace_end(q, kAlign) > ws_bytes) return GT_ERR_WORKSPACE_TOO_SMALL;
+  UnorderedArgs u = unordered_args(q, g, nullptr, ws);
+  u.span = std::max<int64_t>(1, q.chunk / 16);
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  gt_status status = GT_OK;
+  for (auto &x : ev)
+    if (hipEventCreate(&x) != hipSuccess) status = GT_ERR_HIP;
+  if (status == GT_OK && enqueue_hdv_list(q, g, ws, nullptr, st) != hipSuccess) status = GT_ERR_HIP;
+  const uint32_t *nhdv = reinterpret_cast<const uint32_t *>(ws + q.off_u_nhdv);
+  for (int rep = 0; rep < 2 && status == GT_OK; ++rep) {  // the second round is timed
+    for (int way = 0; way < 2 && status == GT_OK; ++way) {
+      u.nhdv = way == 0 ? nhdv : nullptr;
+      if (launch_fill(u.cnt, (uint64_t)q.n, 0u, st) != hipSuccess || hipEventRecord(ev[2 * way], st) != hipSuccess ||
+          launch_hlh_count(u, st) != hipSuccess || hipEventRecord(ev[2 * way + 1], st) != hipSuccess)
+        status = GT_ERR_HIP;
+    }
+  }
+  float t_hlh = 0.f, t_atomic = 0.f;
+  if (status == GT_OK && (hipEventSynchronize(ev[3]) != hipSuccess || hipEventElapsedTime(&t_hlh, ev[0], ev[1]) !=
+                          hipSuccess || hipEventElapsedTime(&t_atomic, ev[2], ev[3]) != hipSuccess))
+    status = GT_ERR_HIP;
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (status == GT_OK) p.strategy = t_hlh <= t_atomic ? GT_STRATEGY_HLH : GT_STRATEGY_ATOMIC;
+  return status;
+}
+
+gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
+                            hipStream_t st) {
+  hipError_t e = hipSuccess;
+#define GT_CHK(x) do { e = (x); if (e != hipSuccess) return GT_ERR_HIP; } while (0)
+#define GT_TIMED(name, x) do { if (prof) GT_CHK(prof->begin(name, st)); GT_CHK(x); if (prof) GT_CHK(prof->end(st)); } while (0)
+  UnorderedArgs u = unordered_args(p, g, &out, ws);
   GT_CHK(launch_fill(u.cnt, (uint64_t)p.n, 0u, st));
   if (p.strategy == GT_STRATEGY_HLH) {
-    // Step 0: the degree sample and the HDV list (at most kmax vertices)
-    uint32_t *nhdv = reinterpret_cast<uint32_t *>(ws + p.off_u_nhdv);
-    SampleArgs sa{};
-    float *feat = nullptr;
-    GT_TIMED("k_sample", enqueue_sampling(g.offsets, g.indices, p.n, p.m, p.pay, p.seed, ws + p.off_u_samp, &feat, st,
-                                          &sa));
-    GT_TIMED("k_hdv_select", launch_hdv_select(sa.keys, sa.counts, sa.mask, p.kmax,
-                                               reinterpret_cast<uint32_t *>(ws + p.off_u_hist),
-                                               reinterpret_cast<uint32_t *>(ws + p.off_u_thr),
-                                               reinterpret_cast<int32_t *>(ws + p.off_u_hdv), nhdv, st));
-    u.nhdv = nhdv;
+    GT_CHK(enqueue_hdv_list(p, g, ws, prof, st));
+    u.nhdv = reinterpret_cast<uint32_t *>(ws + p.off_u_nhdv);
   }
   GT_TIMED("k_hlh_count", launch_hlh_count(u, st));
   GT_TIMED("k_hdv_colscan", launch_hdv_colscan(u, st));
@@ -387,7 +439,7 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   gt_options_t o{};
   if (opt) o = *opt;
   if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_MLP) return GT_ERR_INVALID_ARGUMENT;
-  if (o.strategy < GT_STRATEGY_STABLE || o.strategy > GT_STRATEGY_ATOMIC || o.hdv_max < 0 || o.hdv_max > kHlhMaxHdv)
+  if (o.strategy < GT_STRATEGY_STABLE || o.strategy > GT_STRATEGY_PROBE || o.hdv_max < 0 || o.hdv_max > kHlhMaxHdv)
     return GT_ERR_UNSUPPORTED;
   if (o.policy == GT_POLICY_FIXED) {
     if ((o.fine_bits != 0 && (o.fine_bits < 1 || o.fine_bits > kMaxFineBits)) ||
@@ -401,6 +453,11 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   plan->graphs.resize(count);
   gt_status st = choose_params(plan, graphs, count, o, workspace, workspace_bytes, (hipStream_t)stream);
   if (st != GT_OK) { delete plan; return st; }
+  for (int32_t i = 0; i < count && o.strategy == GT_STRATEGY_PROBE; ++i) {
+    st = probe_strategy(plan->graphs[i], graphs[i], static_cast<char *>(workspace), workspace_bytes,
+                        (hipStream_t)stream);
+    if (st != GT_OK) { delete plan; return st; }
+  }
   size_t base = kAlign;  // byte 0: device status word
   for (int32_t i = 0; i < count; ++i) {
     GraphPlan &p = plan->graphs[i];
@@ -459,6 +516,12 @@ gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t 
   if (digit_bits) *digit_bits = p.max_bits;
   if (passes) *passes = p.passes;
   if (variant) *variant = p.variant;
+  return GT_OK;
+}
+
+gt_status gt_plan_strategy(gt_plan_t plan, int32_t i, int32_t *strategy) {
+  if (plan == nullptr || i < 0 || i >= plan->count || strategy == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  *strategy = plan->graphs[i].strategy;
   return GT_OK;
 }
 

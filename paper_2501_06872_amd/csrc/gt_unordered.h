@@ -17,6 +17,7 @@ struct UnorderedArgs {
   int64_t n, m;
   int64_t chunk;      // edges per chunk (one workgroup each, same map in Steps 1 and 3)
   int64_t nchunks;
+  int64_t span;       // edges Step 1 counts from the start of each chunk (chunk, or less in the probe)
   const int32_t *hdv;     // [kmax] HDV list
   const uint32_t *nhdv;   // device scalar (NULL: no HDVs, Atomic GT)
   int32_t kmax;

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kUNT) void k_hlh_count(UnorderedArgs a) {
   for (uint32_t h = tid; h < nh; h += kUNT) s_cnt[h] = 0u;
   tab.build(a.hdv, nh, tid, kUNT);
   const int64_t beg = (int64_t)blockIdx.x * a.chunk;
-  const int64_t end = beg + a.chunk < a.m ? beg + a.chunk : a.m;
+  const int64_t end = beg + a.span < a.m ? beg + a.span : a.m;
   const uint32_t un = (uint32_t)a.n;
   bool bad = false;
   for (int64_t base = beg; base < end; base += kUNT) {

@@ -99,3 +99,32 @@ def test_hlh_small_table(hip_device):
     O, D, P = gen.rmat(17, 16, seed=9, permute=False, payload=True)
     for k in (1, 16, 300):
         assert_unordered_parity(O, D, P, hip_device, f"rmat17 hdv_max={k}", "hlh", hdv_max=k)
+
+
+def test_probe_picks_a_method_and_stays_exact(hip_device):
+    # the probe of Section IV-C: HLH or Atomic GT, whichever counts faster on
+    # a sixteenth of the chunks; either way the result is the transposition
+    import paper_2501_06872_amd as gt
+    cases = [("star", None), ("rmat18", gen.rmat(18, 16, seed=3, permute=False, payload=True)),
+             ("uniform", gen.uniform(1 << 18, 8, seed=4))]
+    n = 80000
+    star = (np.arange(0, 4 * n + 1, 4, dtype=np.int64), np.full(4 * n, 11, dtype=np.int32), None)
+    cases[0] = ("star", star)
+    for label, (O, D, P) in cases:
+        say(f"[case] probe {label}")
+        g = to_dev(O, D, P, hip_device)
+        plan = gt.Plan([g], gt.make_options(strategy=gt.STRATEGY_PROBE))
+        picked = plan.strategy()
+        say(f"  probe kept {'HLH' if picked == gt.STRATEGY_HLH else 'Atomic GT'}")
+        assert picked in (gt.STRATEGY_HLH, gt.STRATEGY_ATOMIC)
+        T, S, Q = plan.run(*g)
+        torch.cuda.synchronize()
+        rT, rS, rQ = oracle.transpose(O, D, P)
+        T, S = T.cpu().numpy(), S.cpu().numpy()
+        Q = Q.cpu().numpy().view(np.uint32) if Q is not None else None
+        assert np.array_equal(T, rT)
+        cS, cQ = canonical(T, S, Q)
+        oS, oQ = canonical(rT, rS, rQ)
+        assert np.array_equal(cS, oS)
+        if P is not None:
+            assert np.array_equal(cQ, oQ)
