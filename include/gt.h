@@ -246,6 +246,35 @@ gt_status gt_mlp_gradient(const float *params, const float *x, const float *targ
 gt_status gt_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t step, float lr, float beta1,
                       float beta2, float eps, void *stream);
 
+/* ---- Random-access microbenchmark (Section III-B, Fig. 3; the per-access
+ * times of Eq. 2 and Eq. 3, Section IV-B) -------------------------------------
+ * blocks x 256 threads each make `per_thread` accesses of one kind at random
+ * indices of a 32-bit array.  Thread t = block * 256 + lane draws access j at
+ * index ((uint64)r * words) >> 32, r = fmix32(fmix32(seed ^ t) + (j + 1) *
+ * 0x9E3779B9) (fmix32: the 32-bit MurmurHash3 finalizer), so the indices are
+ * a pure function of (seed, t, j) and lie in [0, words).
+ *   GT_ACCESS_READ    acc ^= a[idx]; sink[t] = acc at the end
+ *   GT_ACCESS_WRITE   a[idx] = t (plain stores; the value that survives at an
+ *                     index written by several threads is any one of theirs)
+ *   GT_ACCESS_ATOMIC  atomicAdd(&a[idx], 1) (device-scope, no return value)
+ *   GT_ACCESS_INDEX   acc ^= idx, no memory access (the generator's cost)
+ * memory GT_MEMORY_GLOBAL: a = buf, a device array of `words` words
+ *   (1 <= words <= 2^32); the size picks the level the accesses hit (L2,
+ *   Infinity Cache or HBM).
+ * memory GT_MEMORY_LDS: each workgroup b copies buf[b*words, (b+1)*words) into
+ *   LDS, accesses it there and copies it back; buf holds blocks * words words,
+ *   1 <= words <= 16384 (64 KB of LDS per workgroup).
+ * sink: NULL, or a device array of blocks * 256 words written once per thread
+ * (0 for WRITE and ATOMIC).  blocks in [1, 2^20], per_thread >= 0.  Enqueued
+ * on `stream` without synchronising; the caller times it.  Errors:
+ * GT_ERR_INVALID_ARGUMENT for a NULL buf, a zero size or an unknown kind or
+ * memory, GT_ERR_UNSUPPORTED for words above the limits, GT_ERR_HIP when the
+ * launch fails. */
+enum { GT_ACCESS_READ = 0, GT_ACCESS_WRITE = 1, GT_ACCESS_ATOMIC = 2, GT_ACCESS_INDEX = 3 };
+enum { GT_MEMORY_GLOBAL = 0, GT_MEMORY_LDS = 1 };
+gt_status gt_random_access(uint32_t *buf, uint64_t words, int32_t kind, int32_t memory, uint32_t seed,
+                           int64_t per_thread, int32_t blocks, uint32_t *sink, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,9 @@ baseline leg of ``bench.py`` may import this package; the library under
 * ``transpose_py``    — the definition written out in pure Python (small cases).
 * ``features``        — the degree-sampling pass and feature vector (numpy).
 * ``mlp``             — fp64 forward/backward/Adam of the parameter-choice network.
+* ``random_access``   — replay of the random-access microbenchmark (Fig. 3):
+                        the indices every thread visits and what each access
+                        kind leaves behind.
 """
 import ctypes
 import os

@@ -31,7 +31,7 @@ EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size"
            "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_strategy", "gt_plan_destroy",
            "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
-           "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
+           "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
 NUM_FEATURES = 16
 
 
@@ -89,6 +89,7 @@ def lib():
         L.gt_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
         fl = ctypes.c_float
         L.gt_mlp_adam.argtypes = [vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
+        L.gt_random_access.argtypes = [vp, ctypes.c_uint64, i32, i32, ctypes.c_uint32, ctypes.c_int64, i32, vp, vp]
         L.gt_num_configs.argtypes = []
         L.gt_mlp_num_params.argtypes = []
         L.gt_mlp_work_floats.argtypes = [i32]
@@ -336,3 +337,23 @@ def mlp_gradient(params, x, target, work=None):
 def mlp_adam(params, grad, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(lib().gt_mlp_adam(params.data_ptr(), grad.data_ptr(), m1.data_ptr(), m2.data_ptr(), step, lr, beta1,
                              beta2, eps, _stream_ptr(params.device)), "gt_mlp_adam")
+
+
+# ---- random-access microbenchmark (Fig. 3; the per-access times of Eq. 2 / Eq. 3)
+ACCESS_READ, ACCESS_WRITE, ACCESS_ATOMIC, ACCESS_INDEX = range(4)
+MEMORY_GLOBAL, MEMORY_LDS = range(2)
+THREADS_PER_BLOCK = 256
+
+
+def random_access(buf, words, kind, memory, seed, per_thread, blocks, sink=None):
+    """Enqueue one microbenchmark launch on the current stream.  ``buf`` is a
+    32-bit tensor of at least ``words`` (GLOBAL) or ``blocks * words`` (LDS)
+    elements; ``sink`` None or a 32-bit tensor of ``blocks * 256`` elements."""
+    need = words * (blocks if memory == MEMORY_LDS else 1)
+    if buf.element_size() != 4 or buf.numel() < need:
+        raise ValueError(f"buf needs {need} 32-bit words")
+    if sink is not None and (sink.element_size() != 4 or sink.numel() < blocks * THREADS_PER_BLOCK):
+        raise ValueError(f"sink needs {blocks * THREADS_PER_BLOCK} 32-bit words")
+    _check(lib().gt_random_access(buf.data_ptr(), words, kind, memory, seed & 0xFFFFFFFF, per_thread, blocks,
+                                  sink.data_ptr() if sink is not None else None, _stream_ptr(buf.device)),
+           "gt_random_access")

@@ -3,6 +3,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -32,3 +34,14 @@ def test_byte_model_of_the_dominant_kernels():
     assert bench.kernel_bytes("k_lsd_pass1", n, m, 4, 2) == 12 * m + 10 * m
     assert bench.kernel_bytes("k_final", n, m, 0, 2) == 6 * m + 4 * m + 8 * (n + 1)
     assert bench.path_alg_bytes(n, m, 0) == 2 * (8 * (n + 1) + 4 * m) + 8 * n
+
+
+def test_microbench_levels_and_gpu_requirement():
+    import torch
+    from paper_2501_06872_amd import microbench as mb
+    # every level fits the limits of the entry point
+    for name, (memory, words) in mb.LEVELS.items():
+        assert 1 <= words <= (16384 if memory == 1 else 1 << 32), name
+    if not torch.cuda.is_available():
+        with pytest.raises(SystemExit):
+            mb.main([])
