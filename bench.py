@@ -100,7 +100,7 @@ def path_alg_bytes(n, m, w):
     return 2 * (8 * (n + 1) + (4 + w) * m) + 8 * n
 
 
-def cpu_baseline(workload, O=None, D=None, P=None):
+def cpu_baseline(workload, O=None, D=None, P=None, representation="csr"):
     """The oracle (single-threaded C, untuned) timed on this host.  Workloads
     of up to 2^30 edges: one full oracle run on the bench's own graph
     (~10-30 s); larger ones: a same-family sample of 2^30 edges."""
@@ -118,7 +118,7 @@ def cpu_baseline(workload, O=None, D=None, P=None):
             O, D, P = gen.geometric(kw["n"], kw["ef"], seed=kw["seed"], p=kw["p"])
             desc = f"geometric n=2^{int(np.log2(kw['n']))} ef {kw['ef']}"
     else:
-        desc = f"the full {workload} graph"
+        desc = f"the full {workload} graph" + (" in CSC form" if representation == "csc" else "")
     oracle._load()
     t0 = time.perf_counter()
     oracle.transpose(O, D, P)
@@ -225,6 +225,11 @@ def main():
     ap.add_argument("--strategy", default="stable", choices=["stable", "hlh", "atomic", "probe"],
                     help="hlh / atomic: the paper's unordered methods (list order left to atomics); "
                          "probe: the one of the two that counts faster on a sample of the edges")
+    ap.add_argument("--representation", default="csr", choices=["csr", "csc"],
+                    help="csc: time the transposition of the workload's CSC form (the graph transposed once "
+                         "on the GPU before timing), the CSC / CSC Rnd. inputs of the paper's evaluation")
+    ap.add_argument("--coverage", action="store_true",
+                    help="report the share of edges into the 2048 most frequent destinations")
     ap.add_argument("--check", action="store_true", help="check the output on sampled vertex ranges")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB once before timing (reference for HBM byte counters)")
@@ -250,6 +255,18 @@ def main():
     O_t = torch.from_numpy(O).to(dev)
     D_t = torch.from_numpy(D).to(dev)
     P_t = torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None
+    if args.representation == "csc":
+        O_t, D_t, P_t = gt.transpose(O_t, D_t, P_t)
+        torch.cuda.synchronize()
+        O, D = O_t.cpu().numpy(), D_t.cpu().numpy()
+        P = P_t.cpu().numpy().view(np.uint32) if P_t is not None else None
+        print(f"[bench] input: the CSC form of {args.workload}", file=sys.stderr, flush=True)
+    coverage = None
+    if args.coverage:
+        deg = np.bincount(D, minlength=n)
+        k = min(2048, n)
+        coverage = round(float(np.partition(deg, n - k)[n - k:].sum()) / max(m, 1), 4) if n else 0.0
+        del deg
     strategy = {"stable": gt.STRATEGY_STABLE, "hlh": gt.STRATEGY_HLH, "atomic": gt.STRATEGY_ATOMIC,
                 "probe": gt.STRATEGY_PROBE}[args.strategy]
     opts = gt.make_options(strategy=strategy)
@@ -297,7 +314,8 @@ def main():
     dom_bytes = kernel_bytes(dom, n, m, w, params["passes"])
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     b_alg = path_alg_bytes(n, m, w)
-    traffic, traffic_src = measured_traffic(args.workload, dom)
+    traffic, traffic_src = measured_traffic(args.workload if args.representation == "csr"
+                                            else f"{args.workload}_{args.representation}", dom)
 
     check = None
     if args.check:
@@ -332,7 +350,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": n, "m": m,
-                   "payload_bytes": w, "strategy": args.strategy, "strategy_run": resolved,
+                   "payload_bytes": w, "representation": args.representation, "strategy": args.strategy,
+                   "strategy_run": resolved,
                    "params": params if args.strategy == "stable" else None},
         "path_hbm_frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "path_alg_bytes": b_alg,
@@ -345,9 +364,11 @@ def main():
     }
     if check is not None:
         res["check_sampled_slices"] = check
+    if coverage is not None:
+        res["config"]["coverage_top2048"] = coverage
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(args.workload, O, D, P)
+        res["cpu_baseline"] = cpu_baseline(args.workload, O, D, P, args.representation)
     print(json.dumps(res), flush=True)
 
 
