@@ -165,9 +165,11 @@ __device__ __forceinline__ void status_store(W *p, W v) {
 
 // Exclusive prefix of this tile's `count` over all earlier tiles of the same
 // column (`stride` = number of columns); publishes the aggregate, then the
-// inclusive prefix.  The immediate predecessor is read first (usually it is
-// already inclusive); a longer chain is then read kLookWin tiles per round
-// trip.
+// inclusive prefix.  The predecessors are read kLookWin tiles per round trip,
+// starting with the immediate one: a tile's nearest inclusive predecessor is
+// usually a few dozen tiles back (a tile publishes its inclusive prefix only
+// after its own look-back), so reading the immediate predecessor alone first
+// would cost a round trip that almost never ends the walk.
 constexpr int kLookWin = 8;
 
 // First half: publish this tile's aggregate (tile 0: its inclusive prefix).
@@ -180,7 +182,7 @@ __device__ __forceinline__ void lookback_publish(W *status, int64_t tile, int64_
 
 // Second half: wait for the predecessors, return the exclusive prefix and
 // publish the inclusive one.
-template <typename W>
+template <typename W, int WIN = kLookWin>
 __device__ __forceinline__ uint64_t lookback_wait(W *status, int64_t tile, int64_t stride, int64_t col,
                                                  uint64_t count) {
   using S = Status<W>;
@@ -188,27 +190,13 @@ __device__ __forceinline__ uint64_t lookback_wait(W *status, int64_t tile, int64
   W *mine = status + tile * stride + col;
   uint64_t excl = 0;
   int64_t t = tile - 1;
-  {
-    const W *p = status + t * stride + col;
-    W s = status_load(p);
-    while (!S::ready(s)) {
-      __builtin_amdgcn_s_sleep(1);
-      s = status_load(p);
-    }
-    excl = S::value(s);
-    if (S::is_incl(s)) {
-      status_store(mine, S::incl(excl + count));
-      return excl;
-    }
-    --t;
-  }
   bool done = false;
   while (!done) {
-    W s[kLookWin];
+    W s[WIN];
 #pragma unroll
-    for (int k = 0; k < kLookWin; ++k) s[k] = (t - k >= 0) ? status_load(status + (t - k) * stride + col) : S::incl(0);
+    for (int k = 0; k < WIN; ++k) s[k] = (t - k >= 0) ? status_load(status + (t - k) * stride + col) : S::incl(0);
 #pragma unroll
-    for (int k = 0; k < kLookWin; ++k) {
+    for (int k = 0; k < WIN; ++k) {
       if (!done) {
         const W *p = status + (t - k) * stride + col;
         while (!S::ready(s[k])) {
@@ -219,7 +207,7 @@ __device__ __forceinline__ uint64_t lookback_wait(W *status, int64_t tile, int64
         if (S::is_incl(s[k])) done = true;
       }
     }
-    t -= kLookWin;
+    t -= WIN;
   }
   status_store(mine, S::incl(excl + count));
   return excl;

@@ -214,16 +214,17 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   // rows of 64 consecutive edges; wave w owns rows [w*ITEMS, (w+1)*ITEMS)
   auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
 
-  // Keys, and (later passes) the sources and payload with them, so that
-  // their latency hides behind the ranking and the look-back.  The first
-  // pass derives its sources from the offsets further down.
+  // Keys first.  Without a payload, the sources of later passes are loaded
+  // once the keys are staged: their latency still hides behind the look-back
+  // and the ranking holds 16 registers fewer, which leaves room for three
+  // workgroups per CU.  With a payload, sources and payload are loaded with
+  // the keys (measured faster: the payload's latency is the longer one to
+  // hide).  The first pass derives its sources from the offsets further down.
+  constexpr bool kEarly = PAY;
   uint32_t key[ITEMS];
   uint32_t src_in[CSR_IN ? 1 : ITEMS];
   uint32_t pay_in[PAY ? ITEMS : 1];
-  {
-    const uint32_t *kin = CSR_IN ? reinterpret_cast<const uint32_t *>(a.D) + base : a.in_key + base;
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? kin[row_idx(j)] : 0u;
+  auto load_src_pay = [&]() {
     if constexpr (!CSR_IN) {
       const int32_t *sin = a.in_src + base;
 #pragma unroll
@@ -234,6 +235,12 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) pay_in[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
     }
+  };
+  {
+    const uint32_t *kin = CSR_IN ? reinterpret_cast<const uint32_t *>(a.D) + base : a.in_key + base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? kin[row_idx(j)] : 0u;
+    if constexpr (kEarly) load_src_pay();
   }
   // first pass: the source of the tile's first edge and the first offset
   // each thread inspects for the source marks, also loaded up front
@@ -284,6 +291,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       s_stage[p] = key[j];
     }
   }
+  if constexpr (!kEarly) load_src_pay();
   // look-back per digit across tiles; staged slot i of digit d goes to
   // s_gbase[d] + i
   for (int d = tid; d < radix; d += NT) {
