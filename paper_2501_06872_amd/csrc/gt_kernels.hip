@@ -490,8 +490,20 @@ __global__ __launch_bounds__(WAVES *kWave) void k_big_count(FinalArgs a) {
   const int cnt = (int)((be - cb) < (uint64_t)TILE ? (be - cb) : (uint64_t)TILE);
   for (int v = tid; v < fw; v += NT) s_cnt[v] = 0;
   __syncthreads();
+  // all of the thread's keys are loaded before the first count, so the
+  // loads are in flight together (clamped index, no branch around a load)
   const uint16_t *keys = a.in_key + cb;
-  for (int i = tid; i < cnt; i += NT) atomicAdd(&s_cnt[keys[i] & vmask], 1u);
+  uint32_t kv[ITEMS];
+  if (cnt > 0) {
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const int i = j * NT + tid;
+      kv[j] = keys[i < cnt ? i : cnt - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if (j * NT + tid < cnt) atomicAdd(&s_cnt[kv[j] & vmask], 1u);
+  }
   __syncthreads();
   uint32_t *row = a.cntab + (uint64_t)item * fw;
   for (int v = tid; v < fw; v += NT) row[v] = s_cnt[v];
@@ -573,12 +585,18 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   __syncthreads();
   uint32_t key[ITEMS], lpos[ITEMS];
   // keys and sources at once (the sources are staged later; the payload is
-  // loaded when it is staged, which keeps three workgroups per CU)
+  // loaded when it is staged, which keeps three workgroups per CU).  The key
+  // loads take a clamped index and no branch: a 16-bit load masked inside a
+  // per-row branch is waited for before the next one is issued.
   uint32_t src[ITEMS];
+  if (cnt > 0) {
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? (uint32_t)(a.in_key[cb + row_idx(j)] & vmask) : 0u;
+    for (int j = 0; j < ITEMS; ++j) key[j] = a.in_key[cb + (row_idx(j) < cnt ? row_idx(j) : cnt - 1)];
+  }
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)a.in_src[cb + row_idx(j)] : 0u;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? key[j] & vmask : 0u;
   {
     unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FW;
 #pragma unroll
