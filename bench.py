@@ -43,17 +43,20 @@ CPU_SAMPLE = {
 }
 
 
-def kernel_bytes(name, n, m, w, passes):
+def kernel_bytes(name, n, m, w, passes, packed=False):
     """Algorithmic HBM bytes of one launch of a kernel of the path: what its
-    role requires it to read and write once (w = payload bytes per edge)."""
+    role requires it to read and write once (w = payload bytes per edge).
+    packed: the intermediate between the two passes of a two-pass plan holds
+    6 + w bytes per edge (16-bit key, source word) instead of 8 + w."""
     if name == "k_hist":
         return 4 * m
     if name.startswith("k_lsd_pass"):
         p = int(name[-1])
         first, last = p == 0, p == passes - 1
-        rd = (4 * m + 8 * (n + 1)) if first else 8 * m
+        mid = 6 if packed else 8  # key + source bytes per edge between passes
+        rd = (4 * m + 8 * (n + 1)) if first else mid * m
         rd += w * m
-        wr = (4 + (2 if last else 4) + w) * m
+        wr = ((4 + 2) if last else mid) * m + w * m
         return rd + wr
     if name == "k_final":
         return (4 + 2 + w) * m + (4 + w) * m + 8 * (n + 1)
@@ -275,6 +278,7 @@ def main():
                                variant=args.variant, strategy=strategy)
     plan = gt.Plan([(O_t, D_t, P_t)], opts)
     params = plan.params()
+    params["packed"] = plan.packed()
     resolved = {gt.STRATEGY_STABLE: "stable", gt.STRATEGY_HLH: "hlh", gt.STRATEGY_ATOMIC: "atomic"}[plan.strategy()]
     out = plan.alloc_out(0, P_t.dtype if P_t is not None else None)
     torch.cuda.synchronize()
@@ -311,7 +315,7 @@ def main():
     per_step = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms = prof[dom][0] / prof[dom][1]
-    dom_bytes = kernel_bytes(dom, n, m, w, params["passes"])
+    dom_bytes = kernel_bytes(dom, n, m, w, params["passes"], params["packed"])
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     b_alg = path_alg_bytes(n, m, w)
     traffic, traffic_src = measured_traffic(args.workload if args.representation == "csr"

@@ -190,6 +190,17 @@ gt_status gt_device_status(const void *workspace);
 gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits,
                          int32_t *passes, int32_t *variant);
 
+/* Whether the plan keeps the intermediate between the two partition passes
+ * of graph `i` in packed form (Section II-B, Step 3 split into two stable
+ * passes): 6 + payload bytes per edge (a 16-bit key holding the last pass's
+ * digit and the low fine bits, the source word carrying the remaining fine
+ * bits above the vertex-ID bits) instead of 8 + payload.  Chosen by the plan
+ * for every two-pass graph whose fine bits, last digit bits and vertex-ID
+ * bits add up to at most 48; the output does not depend on it.  `packed`
+ * receives 1 or 0; errors: GT_ERR_INVALID_ARGUMENT for a NULL plan or
+ * output, or `i` outside [0, count). */
+gt_status gt_plan_packed(gt_plan_t plan, int32_t i, int32_t *packed);
+
 /* The strategy a plan runs for graph `i` (GT_STRATEGY_*; a probed plan
  * reports the method the probe kept). */
 gt_status gt_plan_strategy(gt_plan_t plan, int32_t i, int32_t *strategy);

@@ -28,8 +28,8 @@ STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
-           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_strategy", "gt_plan_destroy",
-           "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
+           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
+           "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
 NUM_FEATURES = 16
@@ -78,6 +78,7 @@ def lib():
         L.gt_device_status.argtypes = [vp]
         L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
         L.gt_plan_strategy.argtypes = [vp, i32, P(i32)]
+        L.gt_plan_packed.argtypes = [vp, i32, P(i32)]
         L.gt_plan_destroy.argtypes = [vp]
         L.gt_profile.argtypes = [vp, i32]
         L.gt_profile_read.argtypes = [vp, i32, vp, vp, vp, P(i32)]
@@ -196,6 +197,11 @@ class Plan:
         _check(lib().gt_plan_params(self.handle, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                     ctypes.byref(d)), "gt_plan_params")
         return dict(fine_bits=a.value, digit_bits=b.value, passes=c.value, variant=d.value)
+
+    def packed(self, i=0):
+        out = ctypes.c_int32()
+        _check(lib().gt_plan_packed(self.handle, i, ctypes.byref(out)), "gt_plan_packed")
+        return bool(out.value)
 
     def strategy(self, i=0):
         out = ctypes.c_int32()

@@ -83,8 +83,11 @@ void finalize_params(GraphPlan &p, size_t base) {
   maxb = std::max(maxb, (dbits + kMaxPasses - 1) / kMaxPasses);  // widen digits rather than add passes
   p.passes = (dbits + maxb - 1) / maxb;
   int rem = dbits, shift = fb, maxbits = 0;
+  // digits as even as possible, the narrower ones first: the first pass also
+  // derives the sources from the offsets, and its wider output records (key32
+  // or the packed key16 + source) keep longer runs per digit with fewer digits
   for (int i = 0; i < p.passes; ++i) {
-    const int b = (rem + (p.passes - i) - 1) / (p.passes - i);
+    const int b = rem / (p.passes - i);
     p.bits[i] = b;
     p.shift[i] = shift;
     shift += b;
@@ -93,6 +96,10 @@ void finalize_params(GraphPlan &p, size_t base) {
   }
   p.max_bits = maxbits;
   p.total_bits = dbits;
+  // fine bits + last digit + source bits <= 48 leaves room for the fine bits
+  // above the 16-bit key in the top of the 32-bit source word
+  p.id_bits = L;
+  p.packed = p.passes == 2 && fb + p.bits[1] + L <= 48 && p.bits[1] <= 10;
   // The 16-wave tiles have no 10-bit instance (their lane-mask tables would
   // not fit LDS): such plans use the 8-wave x 16-edge tile for every pass, so
   // that one tile size holds for the tile sources, the look-back status
@@ -228,6 +235,8 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
     LsdArgs a{};
     a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc;
     a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
+    const bool pk = p.packed && (first != last);
+    if (pk && last) a.in_key16 = reinterpret_cast<const uint16_t *>(cur_key);
     if (last) {
       a.out_src = reinterpret_cast<int32_t *>(ws + p.off_b_src);
       a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_b_key);
@@ -236,6 +245,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
       const bool use_a2 = (pass == 1);
       a.out_src = reinterpret_cast<int32_t *>(ws + (use_a2 ? p.off_a2_src : p.off_a_src));
       a.out_key32 = reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_key : p.off_a_key));
+      if (pk) a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_a_key);
       a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_pay : p.off_a_pay)) : nullptr;
     }
     a.shift = p.shift[pass];
@@ -248,8 +258,19 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
     a.lower_bits = p.total_bits - p.bits[p.passes - 1];
     a.fine_mask = (1u << p.fine_bits) - 1u;
     a.bin_start = bins;
+    if (pk) {
+      a.pk_lo = 16 - p.bits[1];
+      a.pk_src_bits = p.id_bits;
+      a.pk_dshift = p.shift[1];
+      a.pk_dbits = p.bits[1];
+      if (last) {  // the packed key holds the digit at bit pk_lo
+        a.shift = a.pk_lo;
+        a.prev_digit_start = digit;
+        a.prev_bits = p.bits[0];
+      }
+    }
     static const char *kLsdNames[kMaxPasses] = {"k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2"};
-    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, p.wide_status, st));
+    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, pk, p.wide_status, st));
     cur_src = a.out_src;
     cur_key = a.out_key32;
     cur_pay = a.out_pay;
@@ -516,6 +537,12 @@ gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t 
   if (digit_bits) *digit_bits = p.max_bits;
   if (passes) *passes = p.passes;
   if (variant) *variant = p.variant;
+  return GT_OK;
+}
+
+gt_status gt_plan_packed(gt_plan_t plan, int32_t i, int32_t *packed) {
+  if (plan == nullptr || i < 0 || i >= plan->count || packed == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  *packed = plan->graphs[i].packed ? 1 : 0;
   return GT_OK;
 }
 

@@ -28,6 +28,7 @@ struct LsdArgs {
   // partitioned input (later passes)
   const int32_t *in_src;
   const uint32_t *in_key;
+  const uint16_t *in_key16;  // packed input (see below)
   const uint32_t *in_pay;
   // output
   int32_t *out_src;
@@ -40,6 +41,14 @@ struct LsdArgs {
   void *status;        // uint32_t words when m < 2^31, else uint64_t
   uint32_t *ticket;
   int64_t m, n;
+  // Packed intermediate of a two-pass plan (6 bytes per edge instead of 8):
+  // the first pass writes key16 = (last digit << pk_lo) | (fine bits mod
+  // 2^pk_lo) and src | (fine bits >> pk_lo) << pk_src_bits; the last pass
+  // reads it back, and takes the first pass's digit of an edge from its
+  // position (prev_digit_start).  pk_dshift / pk_dbits: the last digit.
+  int pk_lo, pk_src_bits, pk_dshift, pk_dbits;
+  const uint64_t *prev_digit_start;
+  int prev_bits;
   // last pass: bin bookkeeping
   int fine_shift;    // = fine bits
   int lower_bits;    // digit bits of the earlier passes
@@ -71,7 +80,8 @@ int64_t lsd_tile_size(int variant);
 // The tile variant that runs digits of up to max_bits bits (variants without
 // an instance for that width map to variant 1).
 int lsd_variant_for(int variant, int max_bits);
-hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide_status,
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool packed,
+                      bool wide_status,
                       hipStream_t st);
 int64_t final_tile_size();
 int64_t scan_tile_size();

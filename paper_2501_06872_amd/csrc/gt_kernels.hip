@@ -17,7 +17,11 @@
 //              coalesced writes.  The first pass reads the CSR and derives
 //              each edge's source from the offsets of the tile (marks in LDS,
 //              running maximum across lanes); the last pass also records
-//              where every fine vertex bin starts.
+//              where every fine vertex bin starts.  Between the two passes of
+//              a two-pass plan an edge takes 6 bytes: a 16-bit key (last
+//              digit, low fine bits) and the source word, whose unused top
+//              bits carry the high fine bits; the last pass recovers the
+//              first pass's digit of an edge from its position.
 //  k_final     Step 3, part 2.  One workgroup per bin of 2^fine_bits
 //              destinations (or per tile-sized chunk of a longer bin, whose
 //              per-chunk counts k_big_count / k_big_scan turn into cursors):
@@ -184,8 +188,12 @@ __global__ __launch_bounds__(1024) void k_digit_scan(const uint64_t *__restrict_
 // ---------------------------------------------------------------------------
 // k_lsd: one stable partition pass by a destination digit.
 // ---------------------------------------------------------------------------
-template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST, typename SW>
+template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST, bool PACKED, typename SW>
 __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
+  // PACKED: the first pass of a two-pass plan writes the packed 6-byte
+  // intermediate (PK_OUT), the last pass reads it (PK_IN)
+  constexpr bool PK_OUT = PACKED && CSR_IN && !LAST;
+  constexpr bool PK_IN = PACKED && !CSR_IN && LAST;
   constexpr int NT = WAVES * kWave;
   constexpr int TILE = NT * ITEMS;
   constexpr int RADIX = 1 << RBITS;
@@ -198,6 +206,11 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   __shared__ uint64_t s_gbase[RADIX];
   __shared__ uint32_t s_misc[NT / kWave + 1];
   __shared__ int64_t s_tile;
+  // PK_IN: positions (relative to the tile) where a digit of the first pass
+  // starts inside the tile; s_fl = {their number, first-pass digit of the
+  // tile's first edge, of the previous tile's last edge}
+  __shared__ uint16_t s_bnd[PK_IN ? kMaxRadix : 1];
+  __shared__ int32_t s_fl[3];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int radix = 1 << a.bits;
@@ -206,6 +219,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   lds_zero16(&s_wcnt[0][0], WAVES * RADIX * 2, tid, NT);
   lds_zero16(s_stage, 2 * WAVES * RADIX * 4, tid, NT);
   if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
+  if (PK_IN && tid < 3) s_fl[tid] = 0;
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t base = tile * TILE;
@@ -236,7 +250,17 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       for (int j = 0; j < ITEMS; ++j) pay_in[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
     }
   };
-  {
+  if constexpr (PK_IN) {
+    // 16-bit loads take a clamped index and no branch (a 16-bit load inside a
+    // per-row branch is waited for before the next is issued); the edge's
+    // position in the tile rides in the upper half
+    const uint16_t *kin = a.in_key16 + base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) key[j] = kin[row_idx(j) < cnt ? row_idx(j) : cnt - 1];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? key[j] | ((uint32_t)row_idx(j) << 16) : 0u;
+    if constexpr (kEarly) load_src_pay();
+  } else {
     const uint32_t *kin = CSR_IN ? reinterpret_cast<const uint32_t *>(a.D) + base : a.in_key + base;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? kin[row_idx(j)] : 0u;
@@ -281,7 +305,9 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets (ends with a barrier)
 
-  // stage keys in sorted order (the keys leave registers before the wait)
+  // stage keys in sorted order (the keys leave registers before the wait);
+  // PK_IN: with the edge's position in the tile in the upper half (its
+  // first-pass digit follows from it)
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (row_idx(j) < cnt) {
@@ -289,6 +315,26 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       const uint32_t p = lpos.get(j) + s_toff[d] + s_wcnt[w][d];
       lpos.set(j, p);
       s_stage[p] = key[j];
+    }
+  }
+  if constexpr (PK_IN) {
+    // first-pass digit of position g: the number of first-pass digits d >= 1
+    // that start at or before g (digit starts are nondecreasing, so empty
+    // digits are skipped).  Counted here for the tile's first edge and the
+    // previous tile's last edge; the digit starts inside the tile are listed.
+    const int prad = 1 << a.prev_bits;
+    uint32_t le_base = 0, le_prev = 0;
+    for (int d = 1 + tid; d < prad; d += NT) {
+      const uint64_t ds = a.prev_digit_start[d];
+      le_base += ds <= (uint64_t)base;
+      le_prev += ds < (uint64_t)base;
+      if (ds > (uint64_t)base && ds < (uint64_t)(base + cnt64)) s_bnd[atomicAdd(&s_fl[0], 1)] = (uint16_t)(ds - base);
+    }
+    le_base = wave_incl_sum(le_base, lane);
+    le_prev = wave_incl_sum(le_prev, lane);
+    if (lane == kWave - 1) {
+      if (le_base) atomicAdd(&s_fl[1], (int32_t)le_base);
+      if (le_prev) atomicAdd(&s_fl[2], (int32_t)le_prev);
     }
   }
   if constexpr (!kEarly) load_src_pay();
@@ -300,7 +346,11 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   }
   __syncthreads();
 
-  // write keys; remember each output slot's digit (two per register)
+  // write keys; remember each output slot's digit (two per register).
+  // PK_OUT: the slot's 16 bits also hold the fine bits that go into the
+  // source word (bits 10..); PK_IN: they are the packed key itself, whose
+  // fine bits are completed from the source word when it is written.
+  const uint32_t pk_lomask = (1u << a.pk_lo) - 1u;
   uint32_t dpk[(ITEMS + 1) / 2];
 #pragma unroll
   for (int k = 0; k < (ITEMS + 1) / 2; ++k) dpk[k] = 0u;
@@ -310,14 +360,27 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     if (i < cnt) {
       const uint32_t kv = s_stage[i];
       const uint32_t d = (kv >> a.shift) & dmask;
-      dpk[k >> 1] |= d << ((k & 1) * 16);
+      uint32_t half = d;
       const uint64_t gp = s_gbase[d] + (uint64_t)i;
-      if (LAST) a.out_key16[gp] = (uint16_t)(kv & a.fine_mask);
-      else a.out_key32[gp] = kv;
+      if constexpr (PK_IN) {
+        half = kv & 0xFFFFu;
+      } else if constexpr (LAST) {
+        a.out_key16[gp] = (uint16_t)(kv & a.fine_mask);
+      } else if constexpr (PK_OUT) {
+        const uint32_t fine = kv & a.fine_mask;
+        const uint32_t d_last = (kv >> a.pk_dshift) & ((1u << a.pk_dbits) - 1u);
+        a.out_key16[gp] = (uint16_t)((d_last << a.pk_lo) | (fine & pk_lomask));
+        half = d | ((fine >> a.pk_lo) << 10);
+      } else {
+        a.out_key32[gp] = kv;
+      }
+      dpk[k >> 1] |= half << ((k & 1) * 16);
     }
   }
+  auto half_of = [&](int k) -> uint32_t { return (dpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu; };
   auto gpos_of = [&](int k, int i) -> uint64_t {
-    const uint32_t d = (dpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
+    const uint32_t h = half_of(k);
+    const uint32_t d = PK_IN ? (h >> a.shift) & dmask : (PK_OUT ? h & 0x3FFu : h);
     return s_gbase[d] + (uint64_t)i;
   };
 
@@ -327,11 +390,25 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     // every digit d the bin (d, fl) starts after the tile's edges of digit d
     // with a smaller lower part (edges of one digit are staged sorted by fl).
     const uint32_t lmask = (1u << a.lower_bits) - 1u;
-    auto fl_of = [&](uint32_t kv) -> uint32_t { return (kv >> a.fine_shift) & lmask; };
+    const uint32_t fl_first = PK_IN ? (uint32_t)s_fl[1] : 0u;
+    const int nbnd = PK_IN ? s_fl[0] : 0;
+    auto fl_of = [&](uint32_t kv) -> uint32_t {
+      if constexpr (PK_IN) {
+        uint32_t fl = fl_first;
+        for (int b = 0; b < nbnd; ++b) fl += (uint32_t)s_bnd[b] <= (kv >> 16);
+        return fl;
+      } else {
+        return (kv >> a.fine_shift) & lmask;
+      }
+    };
     int64_t fl_prev = -1;
-    if (tile > 0) fl_prev = CSR_IN ? (int64_t)fl_of((uint32_t)a.D[base - 1]) : (int64_t)fl_of(a.in_key[base - 1]);
+    if (tile > 0) {
+      if (PK_IN) fl_prev = s_fl[2];
+      else fl_prev = CSR_IN ? (int64_t)fl_of((uint32_t)a.D[base - 1]) : (int64_t)fl_of(a.in_key[base - 1]);
+    }
     int64_t fl_hi;
     if (base + cnt64 >= a.m) fl_hi = (int64_t)lmask;
+    else if (PK_IN) fl_hi = (int64_t)fl_first + nbnd;
     else fl_hi = CSR_IN ? (int64_t)fl_of((uint32_t)a.D[base + cnt64 - 1]) : (int64_t)fl_of(a.in_key[base + cnt64 - 1]);
     const int64_t nown = fl_hi - fl_prev;
     for (int64_t q = tid; q < nown * radix; q += NT) {
@@ -389,10 +466,30 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
       if (row_idx(j) < cnt) s_stage[lpos.get(j)] = src[j];
   }
   __syncthreads();
+  // PK_IN: the fine bits of every slot, completed from its source word, are
+  // written after the sources (two per register until then)
+  uint32_t fpk[PK_IN ? (ITEMS + 1) / 2 : 1];
+#pragma unroll
+  for (int k = 0; k < (PK_IN ? (ITEMS + 1) / 2 : 1); ++k) fpk[k] = 0u;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const int i = k * NT + tid;
-    if (i < cnt) a.out_src[gpos_of(k, i)] = (int32_t)s_stage[i];
+    if (i < cnt) {
+      uint32_t sv = s_stage[i];
+      if constexpr (PK_OUT) sv |= (half_of(k) >> 10) << a.pk_src_bits;
+      if constexpr (PK_IN) {
+        fpk[k >> 1] |= ((half_of(k) & pk_lomask) | ((sv >> a.pk_src_bits) << a.pk_lo)) << ((k & 1) * 16);
+        sv &= (1u << a.pk_src_bits) - 1u;
+      }
+      a.out_src[gpos_of(k, i)] = (int32_t)sv;
+    }
+  }
+  if constexpr (PK_IN) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int i = k * NT + tid;
+      if (i < cnt) a.out_key16[gpos_of(k, i)] = (uint16_t)(fpk[k >> 1] >> ((k & 1) * 16));
+    }
   }
   if (PAY) {
     __syncthreads();
@@ -686,17 +783,20 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
 // launch helpers
 // ---------------------------------------------------------------------------
 template <int WAVES, int ITEMS, int RBITS, typename SW>
-static hipError_t launch_lsd_w(const LsdArgs &a, bool csr_in, bool pay, bool last, hipStream_t st) {
+static hipError_t launch_lsd_w(const LsdArgs &a, bool csr_in, bool pay, bool last, bool pk, hipStream_t st) {
   const int64_t tile = (int64_t)WAVES * kWave * ITEMS;
   const unsigned grid = (unsigned)((a.m + tile - 1) / tile);
   const dim3 blk(WAVES * kWave);
-#define GT_L(C, P, L) hipLaunchKernelGGL((k_lsd<WAVES, ITEMS, RBITS, C, P, L, SW>), dim3(grid), blk, 0, st, a)
+#define GT_L(C, P, L, K) hipLaunchKernelGGL((k_lsd<WAVES, ITEMS, RBITS, C, P, L, K, SW>), dim3(grid), blk, 0, st, a)
+  // the packed intermediate lies between a first pass that is not the last
+  // and a last pass that is not the first
+  if (pk && csr_in == last) return hipErrorInvalidValue;
   if (csr_in) {
-    if (pay) { if (last) GT_L(true, true, true); else GT_L(true, true, false); }
-    else { if (last) GT_L(true, false, true); else GT_L(true, false, false); }
+    if (pay) { if (last) GT_L(true, true, true, false); else if (pk) GT_L(true, true, false, true); else GT_L(true, true, false, false); }
+    else { if (last) GT_L(true, false, true, false); else if (pk) GT_L(true, false, false, true); else GT_L(true, false, false, false); }
   } else {
-    if (pay) { if (last) GT_L(false, true, true); else GT_L(false, true, false); }
-    else { if (last) GT_L(false, false, true); else GT_L(false, false, false); }
+    if (pay) { if (!last) GT_L(false, true, false, false); else if (pk) GT_L(false, true, true, true); else GT_L(false, true, true, false); }
+    else { if (!last) GT_L(false, false, false, false); else if (pk) GT_L(false, false, true, true); else GT_L(false, false, true, false); }
   }
 #undef GT_L
   return hipGetLastError();
@@ -704,9 +804,10 @@ static hipError_t launch_lsd_w(const LsdArgs &a, bool csr_in, bool pay, bool las
 
 // status words: 32-bit when every prefix stays below 2^31, else 64-bit
 template <int WAVES, int ITEMS, int RBITS>
-static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide, hipStream_t st) {
-  return wide ? launch_lsd_w<WAVES, ITEMS, RBITS, uint64_t>(a, csr_in, pay, last, st)
-              : launch_lsd_w<WAVES, ITEMS, RBITS, uint32_t>(a, csr_in, pay, last, st);
+static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool last, bool pk, bool wide,
+                               hipStream_t st) {
+  return wide ? launch_lsd_w<WAVES, ITEMS, RBITS, uint64_t>(a, csr_in, pay, last, pk, st)
+              : launch_lsd_w<WAVES, ITEMS, RBITS, uint32_t>(a, csr_in, pay, last, pk, st);
 }
 
 int64_t lsd_tile_size(int variant) {
@@ -727,23 +828,23 @@ int lsd_variant_for(int variant, int max_bits) {
 // Every (variant, digit width) pair runs an instance whose tile is
 // lsd_tile_size(variant); a pair without one is refused rather than run with
 // another tile size than the plan sized its buffers for.
-hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool wide,
+hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool pk, bool wide,
                       hipStream_t st) {
   if (a.m <= 0) return hipSuccess;
   if (rbits < 1 || rbits > 10 || lsd_variant_for(variant, rbits) != variant) return hipErrorInvalidValue;
   const int rb = rbits <= 8 ? 8 : (rbits <= 9 ? 9 : 10);
 #define GT_V(W, I)                                                                       \
-  return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, wide, st)                      \
-                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, wide, st)           \
-                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, wide, st))
+  return rb == 8 ? launch_lsd_t<W, I, 8>(a, csr_in, pay, last, pk, wide, st)                      \
+                 : (rb == 9 ? launch_lsd_t<W, I, 9>(a, csr_in, pay, last, pk, wide, st)           \
+                            : launch_lsd_t<W, I, 10>(a, csr_in, pay, last, pk, wide, st))
   switch (variant) {
     case 2:  // 16 waves x 8 edges, digits of up to 9 bits
-      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, wide, st)
-                     : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, wide, st);
+      return rb == 8 ? launch_lsd_t<16, 8, 8>(a, csr_in, pay, last, pk, wide, st)
+                     : launch_lsd_t<16, 8, 9>(a, csr_in, pay, last, pk, wide, st);
     case 3: GT_V(8, 8);
     case 4:  // 16 waves x 16 edges (16K-edge tiles), digits of up to 9 bits
-      return rb == 8 ? launch_lsd_t<16, 16, 8>(a, csr_in, pay, last, wide, st)
-                     : launch_lsd_t<16, 16, 9>(a, csr_in, pay, last, wide, st);
+      return rb == 8 ? launch_lsd_t<16, 16, 8>(a, csr_in, pay, last, pk, wide, st)
+                     : launch_lsd_t<16, 16, 9>(a, csr_in, pay, last, pk, wide, st);
     default: GT_V(8, 16);
   }
 #undef GT_V

@@ -22,6 +22,11 @@ struct GraphPlan {
   int passes, bits[3], shift[3], max_bits, total_bits;
   int64_t nbins_total, nbins, tile, ntiles;
   bool wide_status;  // 64-bit look-back words (m >= 2^31)
+  // two-pass plans whose key and source bits fit 48: the intermediate
+  // between the passes is packed into 6 bytes per edge (16-bit key + source
+  // word carrying the high fine bits); id_bits = bits of a vertex ID
+  bool packed = false;
+  int id_bits = 0;
   bool force_wide;
   // workspace byte offsets (relative to the workspace start)
   size_t off_err, off_ticket, off_part, off_digit, off_dtot, off_bin, off_status, off_tsrc;

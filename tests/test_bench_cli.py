@@ -32,6 +32,9 @@ def test_byte_model_of_the_dominant_kernels():
     assert bench.kernel_bytes("k_lsd_pass0", n, m, 0, 2) == 4 * m + 8 * (n + 1) + 8 * m
     # last pass with payload: key32 + source + payload in, key16 + source + payload out
     assert bench.kernel_bytes("k_lsd_pass1", n, m, 4, 2) == 12 * m + 10 * m
+    # packed intermediate of a two-pass plan: 16-bit key + source word between the passes
+    assert bench.kernel_bytes("k_lsd_pass0", n, m, 0, 2, packed=True) == 4 * m + 8 * (n + 1) + 6 * m
+    assert bench.kernel_bytes("k_lsd_pass1", n, m, 4, 2, packed=True) == 10 * m + 10 * m
     assert bench.kernel_bytes("k_final", n, m, 0, 2) == 6 * m + 4 * m + 8 * (n + 1)
     assert bench.path_alg_bytes(n, m, 0) == 2 * (8 * (n + 1) + 4 * m) + 8 * n
 

@@ -140,6 +140,86 @@ def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
     assert_parity(O, D, P, hip_device, f"random n={n} avg={avg} skew={skew}")
 
 
+@pytest.mark.parametrize("payload", [False, True])
+def test_two_pass_intermediate_wide_ids(hip_device, payload):
+    # 26-bit vertex IDs, 9 fine bits, digits of 8 and 9 bits: the key of the
+    # intermediate between the passes cannot hold all fine bits, so the top
+    # ones travel in the source word; a hub and a dense block make the
+    # first-pass digits uneven
+    rng = np.random.default_rng(5)
+    n = (1 << 25) + 3
+    m = 3_000_000
+    src = np.sort(rng.integers(0, n, size=m))
+    D = rng.integers(0, n, size=m).astype(np.int32)
+    D[: m // 5] = n - 1
+    D[m // 5: m // 3] = rng.integers(0, 1 << 12, size=m // 3 - m // 5)
+    rng.shuffle(D)
+    order = np.lexsort((D, src))
+    src, D = src[order], D[order]
+    O = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int64)
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
+    params = assert_parity(O, D, P, hip_device, "26-bit ids, two passes", policy=1, fine_bits=9, digit_bits=9,
+                           variant=1)
+    assert params["passes"] == 2, params
+
+
+def test_two_pass_intermediate_one_tile(hip_device):
+    # every digit boundary of the first pass falls inside the only tile
+    rng = np.random.default_rng(8)
+    O, D, P = random_csr(rng, 5000, 1.2, payload=True)
+    for fine_bits, digit_bits in ((1, 6), (4, 4), (2, 7)):  # packed, three passes, packed
+        assert_parity(O, D, P, hip_device, "one tile, two passes", policy=1, fine_bits=fine_bits,
+                      digit_bits=digit_bits, variant=1)
+
+
+@pytest.mark.parametrize("payload", [False, True])
+def test_sparse_sources_many_per_tile(hip_device, payload):
+    # a dense head, then a long stretch of sources with zero or one edge: a
+    # partition tile of the first pass spans up to ~10^5 sources there
+    rng = np.random.default_rng(31)
+    n = 400_000
+    deg = np.zeros(n, dtype=np.int64)
+    deg[:2000] = rng.integers(0, 40, size=2000)
+    tail = rng.random(n - 2000) < 0.05
+    deg[2000:][tail] = 1
+    deg[-1] = 3
+    O = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    m = int(O[-1])
+    D = rng.integers(0, n, size=m).astype(np.int32)
+    for u in np.flatnonzero(deg > 1):
+        D[O[u]:O[u + 1]].sort()
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
+    assert_parity(O, D, P, hip_device, "sparse sources")
+    assert_parity(O, D, P, hip_device, "sparse sources, 3 passes", policy=1, fine_bits=4, digit_bits=5, variant=1)
+
+
+@pytest.mark.parametrize("payload", [False, True])
+def test_bin_sizes_around_the_final_item(hip_device, payload):
+    # 16 bins of 512 destinations (fine_bits 9) whose edge counts straddle
+    # the k_final work item (empty, one row, partial rows, small bins spread
+    # over the waves, just below / at / above one and two items), with a hub
+    # inside some bins
+    rng = np.random.default_rng(77)
+    sizes = [0, 1, 63, 64, 65, 500, 4097, 8191, 8192, 8193, 9215, 9216, 9217, 18432, 18433, 30000]
+    n = 512 * 64  # 48 more bins, empty: six coarse bits
+    src, dst = [], []
+    for b, sz in enumerate(sizes):
+        d = rng.integers(0, 512, size=sz)
+        if b % 3 == 0:
+            d[: sz // 4] = 7  # a heavy destination
+        dst.append(b * 512 + d)
+        src.append(rng.integers(0, n, size=sz))
+    src = np.concatenate(src).astype(np.int64)
+    dst = np.concatenate(dst).astype(np.int32)
+    order = np.lexsort((dst, src))
+    src, D = src[order], dst[order]
+    O = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int64)
+    P = rng.integers(0, 2**32, size=D.size, dtype=np.uint64).astype(np.uint32) if payload else None
+    for digit_bits in (4, 8):  # two passes, one pass
+        assert_parity(O, D, P, hip_device, "bins around the item size", policy=1, fine_bits=9,
+                      digit_bits=digit_bits, variant=1)
+
+
 @pytest.mark.parametrize("fine_bits,digit_bits,variant", [
     (1, 4, 1), (4, 6, 3), (8, 10, 2), (9, 4, 1), (5, 10, 3), (7, 8, 2), (9, 10, 1), (6, 5, 1), (8, 9, 4), (3, 6, 4),
     (7, 10, 4), (7, 10, 2),  # one 10-bit pass: the 16-wave variants run the 8-wave tile
