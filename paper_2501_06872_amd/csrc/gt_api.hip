@@ -142,7 +142,7 @@ void finalize_params(GraphPlan &p, size_t base) {
   p.max_items = p.nbins + (p.m + final_tile_size() - 1) / final_tile_size();
   p.off_nch = take(4 * nb);
   p.off_ibase = take(4 * nb);
-  p.off_ibin = take(4 * (size_t)std::max<int64_t>(p.max_items, 1));
+  p.off_ibin = take(16 * (size_t)std::max<int64_t>(p.max_items, 1));  // item descriptors
   p.off_itotal = take(4 * 4);
   p.off_sstatus = take(8 * (size_t)((p.nbins + scan_tile_size() - 1) / scan_tile_size() + 1));
   p.off_cntab = take(4 * (size_t)std::max<int64_t>(p.max_items, 1) * ((size_t)1 << p.fine_bits));
@@ -220,8 +220,11 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   HistArgs h{};
   h.passes = p.passes;
   for (int i = 0; i < p.passes; ++i) { h.shift[i] = p.shift[i]; h.bits[i] = p.bits[i]; }
-  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, kHistBlocks, part, err, st));
-  GT_TIMED("k_digit_scan", launch_digit_scan(part, kHistBlocks, h, reinterpret_cast<uint64_t *>(ws + p.off_dtot),
+  // one histogram workgroup per 4096 edges, at most kHistBlocks: a small
+  // graph neither launches nor sums partial histograms it has no edges for
+  const int hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, (p.m + 4095) / 4096));
+  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, hist_blocks, part, err, st));
+  GT_TIMED("k_digit_scan", launch_digit_scan(part, hist_blocks, h, reinterpret_cast<uint64_t *>(ws + p.off_dtot),
                                              digit, bins, p.nbins_total, p.m, st));
   GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
 
@@ -284,7 +287,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   f.n = p.n; f.m = p.m; f.nbins = p.nbins; f.fine_bits = p.fine_bits;
   f.nch = reinterpret_cast<uint32_t *>(ws + p.off_nch);
   f.item_base = reinterpret_cast<uint32_t *>(ws + p.off_ibase);
-  f.item_bin = reinterpret_cast<uint32_t *>(ws + p.off_ibin);
+  f.item_desc = reinterpret_cast<uint4 *>(ws + p.off_ibin);
   f.total_items = reinterpret_cast<uint32_t *>(ws + p.off_itotal);
   f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
   f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);

@@ -69,7 +69,9 @@ struct FinalArgs {
   // work items: bins longer than one tile are split into tile-sized chunks
   uint32_t *nch;          // [nbins] chunks per bin
   uint32_t *item_base;    // [nbins] first item of each bin
-  uint32_t *item_bin;     // [max items] bin of each item
+  // [max items] per work item: x, y = first edge (64-bit), z = bin,
+  // w = edge count | 2^31 when the item is a whole bin
+  uint4 *item_desc;
   uint32_t *total_items;  // device scalar
   uint32_t *cntab;        // [max items][2^fine_bits] per-chunk vertex counts -> prefixes
   uint32_t *bigbins;      // [max big bins] bins split into several chunks

@@ -160,8 +160,21 @@ __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict
   if (p >= h.passes) return;
   const int radix = 1 << h.bits[p];
   uint64_t s = 0;
-  if (d < radix)
-    for (int b = q; b < nblocks; b += 4) s += part[(int64_t)b * kMaxPasses * kMaxRadix + p * kMaxRadix + d];
+  if (d < radix) {
+    // U partials in flight per thread
+    constexpr int U = 8;
+    constexpr int64_t kRow = (int64_t)kMaxPasses * kMaxRadix;
+    const uint32_t *col = part + p * kMaxRadix + d;
+    int b = q;
+    for (; b + 4 * (U - 1) < nblocks; b += 4 * U) {
+      uint32_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = col[(int64_t)(b + 4 * u) * kRow];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; b < nblocks; b += 4) s += col[(int64_t)b * kRow];
+  }
   s_sum[q][tid & 63] = s;
   __syncthreads();
   if (q == 0 && d < radix) totals[p * kMaxRadix + d] = s_sum[0][tid] + s_sum[1][tid] + s_sum[2][tid] + s_sum[3][tid];
@@ -555,14 +568,21 @@ __global__ void k_bin_items(const uint64_t *bin_start, int64_t nbins, int64_t ti
   if (f == nbins - 1) T[n] = m;
 }
 
-// Item -> bin map, and the list of bins split into several chunks (its order
-// is irrelevant: every big bin is processed independently).
-__global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, int64_t nbins, uint32_t *item_bin,
-                           uint32_t *bigbins, uint32_t *nbig) {
+// Work-item descriptors (first edge, bin, edge count, whole-bin flag), so
+// that k_big_count and k_final find their edges with one load instead of a
+// chain item -> bin -> bin start; and the list of bins split into several
+// chunks (its order is irrelevant: every big bin is processed independently).
+__global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, const uint64_t *bin_start,
+                           int64_t nbins, int64_t tile, uint4 *item_desc, uint32_t *bigbins, uint32_t *nbig) {
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nbins) return;
   const uint32_t b = item_base[f], c = nch[f];
-  for (uint32_t k = 0; k < c; ++k) item_bin[b + k] = (uint32_t)f;
+  const uint64_t bs = bin_start[f], be = bin_start[f + 1];
+  for (uint32_t k = 0; k < c; ++k) {
+    const uint64_t cb = bs + (uint64_t)k * (uint64_t)tile;
+    const uint32_t cnt = (uint32_t)(be - cb < (uint64_t)tile ? be - cb : (uint64_t)tile);
+    item_desc[b + k] = make_uint4((uint32_t)cb, (uint32_t)(cb >> 32), (uint32_t)f, cnt | (c == 1 ? 0x80000000u : 0u));
+  }
   if (c > 1) bigbins[atomicAdd(nbig, 1u)] = (uint32_t)f;
 }
 
@@ -574,17 +594,14 @@ __global__ __launch_bounds__(WAVES *kWave) void k_big_count(FinalArgs a) {
   constexpr int FW = 1 << FBITS;
   __shared__ uint32_t s_cnt[FW];
   const int64_t item = blockIdx.x;
-  if (item >= (int64_t)*a.total_items) return;
-  const uint32_t f = a.item_bin[item];
-  const uint32_t nch = a.nch[f];
-  if (nch == 1) return;
+  const uint32_t total = *a.total_items;
+  const uint4 dsc = a.item_desc[item];  // grid = the most items a plan can have
+  if (item >= (int64_t)total || (dsc.w >> 31)) return;  // whole bins have no chunk counts
   const int tid = threadIdx.x;
   const int fw = 1 << a.fine_bits;
   const uint32_t vmask = (uint32_t)fw - 1u;
-  const uint32_t first_item = a.item_base[f];
-  const uint64_t bs = a.bin_start[f], be = a.bin_start[f + 1];
-  const uint64_t cb = bs + (uint64_t)(item - first_item) * TILE;
-  const int cnt = (int)((be - cb) < (uint64_t)TILE ? (be - cb) : (uint64_t)TILE);
+  const uint64_t cb = (uint64_t)dsc.x | ((uint64_t)dsc.y << 32);
+  const int cnt = (int)(dsc.w & 0x7FFFFFFFu);
   for (int v = tid; v < fw; v += NT) s_cnt[v] = 0;
   __syncthreads();
   // all of the thread's keys are loaded before the first count, so the
@@ -661,21 +678,23 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   __shared__ uint32_t s_w32[NT / kWave + 1];
 
   const int64_t item = blockIdx.x;
-  if (item >= (int64_t)*a.total_items) return;
+  const uint32_t total = *a.total_items;
+  const uint4 dsc = a.item_desc[item];  // grid = the most items a plan can have
+  if (item >= (int64_t)total) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const uint32_t f = a.item_bin[item];
-  const uint32_t nch = a.nch[f];
+  const uint32_t f = dsc.z;
+  const bool whole = (dsc.w >> 31) != 0u;
   const int fw = 1 << a.fine_bits;
   const uint32_t vmask = (uint32_t)fw - 1u;
-  const uint64_t bs = a.bin_start[f], be = a.bin_start[f + 1];
-  const uint64_t cb = bs + (uint64_t)(item - a.item_base[f]) * TILE;
-  const int cnt = (int)((be - cb) < (uint64_t)TILE ? (be - cb) : (uint64_t)TILE);
+  const uint64_t cb = (uint64_t)dsc.x | ((uint64_t)dsc.y << 32);
+  const uint64_t bs = cb;  // a whole bin starts at its item's first edge
+  const int cnt = (int)(dsc.w & 0x7FFFFFFFu);
   const int64_t v0 = (int64_t)f << a.fine_bits;
   auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
 
   lds_zero16(&s_wcnt[0][0], WAVES * FW * 2, tid, NT);
   lds_zero16(s_stage, 2 * WAVES * FW * 4, tid, NT);
-  if (nch > 1) {
+  if (!whole) {
     const uint32_t *row = a.cntab + (uint64_t)item * fw;
     for (int v = tid; v < fw; v += NT) s_cur[v] = (uint64_t)a.T[v0 + v < a.n ? v0 + v : a.n] + row[v];
   }
@@ -719,7 +738,6 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   // A whole bin: its counts are the in-degrees of its vertices, and its
   // staged order is its final CSC order, so staged slot i goes to bs + i.
   // A chunk of a big bin: slot i of vertex v goes to s_cur[v] + i.
-  const bool whole = nch == 1;
   for (int v = tid; v < fw; v += NT) {
     if (whole) {
       if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_toff[v]);
@@ -860,7 +878,7 @@ hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st) {
 
 hipError_t launch_item_map(const FinalArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_item_map, dim3((unsigned)((a.nbins + 255) / 256)), dim3(256), 0, st, a.nch, a.item_base,
-                     a.nbins, a.item_bin, a.bigbins, a.nbig);
+                     a.bin_start, a.nbins, final_tile_size(), a.item_desc, a.bigbins, a.nbig);
   return hipGetLastError();
 }
 
