@@ -13,10 +13,12 @@
 //              destination digit (least significant digit first), tile by
 //              tile: coalesced loads, in-wave stable ranking through an LDS
 //              table of lane masks, per-wave LDS counters, decoupled
-//              look-back across tiles for the per-digit prefix, LDS-staged
-//              coalesced writes.  The first pass reads the CSR and derives
-//              each edge's source from the offsets of the tile (marks in LDS,
-//              running maximum across lanes); the last pass also records
+//              look-back across tiles for the per-digit prefix (the first
+//              pass takes its tiles from the end and sums the tiles behind
+//              each one), LDS-staged coalesced writes.  The first pass reads
+//              the CSR and derives each edge's source from the offsets of
+//              the tile (marks in LDS, running maximum across lanes); the
+//              last pass also records
 //              where every fine vertex bin starts.  Between the two passes of
 //              a two-pass plan an edge takes 6 bytes: a 16-bit key (last
 //              digit, low fine bits) and the source word, whose unused top
@@ -234,7 +236,14 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
   if (PK_IN && tid < 3) s_fl[tid] = 0;
   __syncthreads();
-  const int64_t tile = s_tile;
+  // The first pass takes its tiles from the end of the edge array: the
+  // sources of a natural-order graph thin out towards high IDs, and a tile
+  // there fills its sources from up to ~10^5 offsets, so those tiles start
+  // first instead of closing the launch.  Its look-back then runs over the
+  // tiles behind it (suffix counts), in the order the tiles are taken.
+  const int64_t ntiles = (a.m + TILE - 1) / TILE;
+  const int64_t order = s_tile;  // position in the look-back chain
+  const int64_t tile = CSR_IN ? ntiles - 1 - order : order;
   const int64_t base = tile * TILE;
   const int64_t cnt64 = a.m - base < TILE ? a.m - base : TILE;
   const int cnt = (int)cnt64;
@@ -311,7 +320,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     }
     s_tot[d] = run;
     s_toff[d] = run;
-    lookback_publish<SW>(static_cast<SW *>(a.status), tile, radix, d, run);
+    lookback_publish<SW>(static_cast<SW *>(a.status), order, radix, d, run);
   }
   // the scan below reads s_toff in blocks of radix / NT entries per thread,
   // so with more digits than threads it reads other threads' writes
@@ -354,8 +363,10 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   // look-back per digit across tiles; staged slot i of digit d goes to
   // s_gbase[d] + i
   for (int d = tid; d < radix; d += NT) {
-    const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), tile, radix, d, s_tot[d]);
-    s_gbase[d] = a.digit_start[d] + excl - s_toff[d];
+    const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), order, radix, d, s_tot[d]);
+    // ascending tiles: digit start + the earlier tiles' count; descending
+    // (first pass): digit end - the later tiles' count - this tile's count
+    s_gbase[d] = CSR_IN ? a.digit_start[d + 1] - excl - s_tot[d] - s_toff[d] : a.digit_start[d] + excl - s_toff[d];
   }
   __syncthreads();
 

@@ -34,8 +34,10 @@ def gpu_transpose(O, D, P, dev, **opt):
     T, S, Q = plan.run(O_t, D_t, P_t)
     torch.cuda.synchronize()
     st = plan.device_status()
+    params = plan.params()
+    params["packed"] = plan.packed()
     return (T.cpu().numpy(), S.cpu().numpy(), Q.cpu().numpy().view(np.uint32) if Q is not None else None,
-            st, plan.params())
+            st, params)
 
 
 def assert_parity(O, D, P, dev, label, **opt):
@@ -160,16 +162,17 @@ def test_two_pass_intermediate_wide_ids(hip_device, payload):
     P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
     params = assert_parity(O, D, P, hip_device, "26-bit ids, two passes", policy=1, fine_bits=9, digit_bits=9,
                            variant=1)
-    assert params["passes"] == 2, params
+    assert params["passes"] == 2 and params["packed"], params
 
 
 def test_two_pass_intermediate_one_tile(hip_device):
     # every digit boundary of the first pass falls inside the only tile
     rng = np.random.default_rng(8)
     O, D, P = random_csr(rng, 5000, 1.2, payload=True)
-    for fine_bits, digit_bits in ((1, 6), (4, 4), (2, 7)):  # packed, three passes, packed
-        assert_parity(O, D, P, hip_device, "one tile, two passes", policy=1, fine_bits=fine_bits,
-                      digit_bits=digit_bits, variant=1)
+    for fine_bits, digit_bits, packed in ((1, 6, True), (4, 4, False), (2, 7, True)):  # three passes: not packed
+        params = assert_parity(O, D, P, hip_device, "one tile, two passes", policy=1, fine_bits=fine_bits,
+                               digit_bits=digit_bits, variant=1)
+        assert params["packed"] == packed, params
 
 
 @pytest.mark.parametrize("payload", [False, True])
