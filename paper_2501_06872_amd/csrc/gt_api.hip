@@ -83,11 +83,11 @@ void finalize_params(GraphPlan &p, size_t base) {
   maxb = std::max(maxb, (dbits + kMaxPasses - 1) / kMaxPasses);  // widen digits rather than add passes
   p.passes = (dbits + maxb - 1) / maxb;
   int rem = dbits, shift = fb, maxbits = 0;
-  // digits as even as possible, the narrower ones first: the first pass also
-  // derives the sources from the offsets, and its wider output records (key32
-  // or the packed key16 + source) keep longer runs per digit with fewer digits
+  // digits as even as possible, the wider ones first (measured: on 2^26-
+  // vertex graphs 9 + 8 bits beat 8 + 9 by 1 % on natural-order R-MAT and
+  // lose 0.3-0.5 % on uniform and permuted graphs)
   for (int i = 0; i < p.passes; ++i) {
-    const int b = rem / (p.passes - i);
+    const int b = (rem + (p.passes - i) - 1) / (p.passes - i);
     p.bits[i] = b;
     p.shift[i] = shift;
     shift += b;

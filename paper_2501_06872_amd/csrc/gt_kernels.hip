@@ -625,9 +625,40 @@ __global__ __launch_bounds__(WAVES *kWave) void k_big_count(FinalArgs a) {
       const int i = j * NT + tid;
       kv[j] = keys[i < cnt ? i : cnt - 1];
     }
+    // In a hub's chunk most lanes of a row (64 consecutive edges of one wave)
+    // share one destination, and 64 lanes updating one LDS counter would be
+    // serialised: a wave whose first row is dominated by lane 0's
+    // destination adds, in every row, the lanes that share lane 0's
+    // destination with one atomic.  Other waves count lane by lane.
+    const int lane = tid & (kWave - 1);
+    auto dominated = [&](int j, uint32_t &k0, unsigned long long &same) {
+      const bool in = j * NT + tid < cnt;
+      const uint32_t k = kv[j] & vmask;
+      k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+      same = __ballot(in && k == k0);
+      return __popcll(same) >= 16;
+    };
+    uint32_t k00;
+    unsigned long long same0;
+    if (dominated(0, k00, same0)) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-      if (j * NT + tid < cnt) atomicAdd(&s_cnt[kv[j] & vmask], 1u);
+      for (int j = 0; j < ITEMS; ++j) {
+        const bool in = j * NT + tid < cnt;
+        const uint32_t k = kv[j] & vmask;
+        uint32_t k0;
+        unsigned long long same;
+        if (dominated(j, k0, same)) {
+          if (lane == 0) atomicAdd(&s_cnt[k0], (uint32_t)__popcll(same));
+          if (in && k != k0) atomicAdd(&s_cnt[k], 1u);
+        } else if (in) {
+          atomicAdd(&s_cnt[k], 1u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j)
+        if (j * NT + tid < cnt) atomicAdd(&s_cnt[kv[j] & vmask], 1u);
+    }
   }
   __syncthreads();
   uint32_t *row = a.cntab + (uint64_t)item * fw;

@@ -142,6 +142,25 @@ def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
     assert_parity(O, D, P, hip_device, f"random n={n} avg={avg} skew={skew}")
 
 
+@pytest.mark.parametrize("share", [1.0, 0.9, 0.3])
+def test_hub_rows(hip_device, share):
+    # one destination takes `share` of a bin spanning many work items: rows of
+    # the bin are wholly, mostly or partly that destination (the single-key
+    # row paths of the chunk counts and of the placement ranking)
+    rng = np.random.default_rng(int(share * 100))
+    n, m = 4096, 70_000
+    src = np.sort(rng.integers(0, n, size=m))
+    D = rng.integers(0, 512, size=m).astype(np.int32)
+    D[rng.random(m) < share] = 5
+    D[: 1000] = rng.integers(512, n, size=1000)
+    order = np.lexsort((D, src))
+    src, D = src[order], D[order]
+    O = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int64)
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32)
+    assert_parity(O, D, P, hip_device, f"hub rows {share}", policy=1, fine_bits=9, digit_bits=8, variant=1)
+    assert_parity(O, D, None, hip_device, f"hub rows {share}, no payload")
+
+
 @pytest.mark.parametrize("payload", [False, True])
 def test_two_pass_intermediate_wide_ids(hip_device, payload):
     # 26-bit vertex IDs, 9 fine bits, digits of 8 and 9 bits: the key of the
