@@ -148,6 +148,8 @@ void finalize_params(GraphPlan &p, size_t base) {
   p.off_cntab = take(4 * (size_t)std::max<int64_t>(p.max_items, 1) * ((size_t)1 << p.fine_bits));
   p.max_big = std::min<int64_t>(p.nbins, p.m / final_tile_size() + 1);
   p.off_big = take(4 * (size_t)std::max<int64_t>(p.max_big, 1));
+  p.max_huge = std::min<int64_t>(p.nbins, p.m / (final_tile_size() * kHugeChunks) + 1);
+  p.off_huge = take(4 * (size_t)std::max<int64_t>(p.max_huge, 1));
   p.ws_end = off;
 }
 
@@ -292,15 +294,17 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
   f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
   f.nbig = f.total_items + 2;
+  f.hugebins = reinterpret_cast<uint32_t *>(ws + p.off_huge);
+  f.nhuge = f.total_items + 3;
   uint32_t *sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
   const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
   GT_TIMED("k_bin_items", launch_bin_items(f, st));
   GT_CHK(launch_fill(sstatus, (uint64_t)scan_tiles, 0u, st));
-  GT_CHK(launch_fill(f.total_items + 1, 2, 0u, st));  // scan ticket, big-bin count
+  GT_CHK(launch_fill(f.total_items + 1, 3, 0u, st));  // scan ticket, big- and huge-bin counts
   GT_TIMED("k_scan_u32", launch_scan_u32(f.nch, f.item_base, p.nbins, sstatus, f.total_items + 1, f.total_items, st));
   GT_TIMED("k_item_map", launch_item_map(f, st));
   GT_TIMED("k_big_count", launch_big_count(f, p.max_items, st));
-  GT_TIMED("k_big_scan", launch_big_scan(f, p.max_big, st));
+  GT_TIMED("k_big_scan", launch_big_scan(f, p.max_big, p.max_huge, st));
   GT_TIMED("k_final", launch_final(f, p.max_items, p.pay, st));
 #undef GT_TIMED
 #undef GT_CHK

@@ -74,8 +74,10 @@ struct FinalArgs {
   uint4 *item_desc;
   uint32_t *total_items;  // device scalar
   uint32_t *cntab;        // [max items][2^fine_bits] per-chunk vertex counts -> prefixes
-  uint32_t *bigbins;      // [max big bins] bins split into several chunks
+  uint32_t *bigbins;      // [max big bins] bins split into 2..kHugeChunks chunks
   uint32_t *nbig;         // device scalar
+  uint32_t *hugebins;     // [max huge bins] bins split into more than kHugeChunks chunks
+  uint32_t *nhuge;        // device scalar
 };
 
 int64_t lsd_tile_size(int variant);
@@ -92,7 +94,9 @@ hipError_t launch_item_map(const FinalArgs &a, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint32_t *status, uint32_t *ticket,
                            uint32_t *total, hipStream_t st);
 hipError_t launch_big_count(const FinalArgs &a, int64_t max_items, hipStream_t st);
-hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st);
+// bins of more chunks than this are scanned by a wider launch of k_big_scan
+constexpr int kHugeChunks = 64;
+hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, int64_t max_huge, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, int64_t max_items, bool pay, hipStream_t st);
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err, hipStream_t st);

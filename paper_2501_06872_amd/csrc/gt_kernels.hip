@@ -584,7 +584,8 @@ __global__ void k_bin_items(const uint64_t *bin_start, int64_t nbins, int64_t ti
 // chain item -> bin -> bin start; and the list of bins split into several
 // chunks (its order is irrelevant: every big bin is processed independently).
 __global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, const uint64_t *bin_start,
-                           int64_t nbins, int64_t tile, uint4 *item_desc, uint32_t *bigbins, uint32_t *nbig) {
+                           int64_t nbins, int64_t tile, uint4 *item_desc, uint32_t *bigbins, uint32_t *nbig,
+                           uint32_t *hugebins, uint32_t *nhuge) {
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f >= nbins) return;
   const uint32_t b = item_base[f], c = nch[f];
@@ -594,7 +595,19 @@ __global__ void k_item_map(const uint32_t *nch, const uint32_t *item_base, const
     const uint32_t cnt = (uint32_t)(be - cb < (uint64_t)tile ? be - cb : (uint64_t)tile);
     item_desc[b + k] = make_uint4((uint32_t)cb, (uint32_t)(cb >> 32), (uint32_t)f, cnt | (c == 1 ? 0x80000000u : 0u));
   }
-  if (c > 1) bigbins[atomicAdd(nbig, 1u)] = (uint32_t)f;
+  // append to the lists with one atomic per wave and list
+  const int lane = lane_id();
+  auto push = [&](bool want, uint32_t *list, uint32_t *counter) {
+    const unsigned long long mask = __ballot(want);
+    if (mask == 0ull) return;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t first = 0;
+    if (lane == leader) first = atomicAdd(counter, (uint32_t)__popcll(mask));
+    first = (uint32_t)__shfl((int)first, leader);
+    if (want) list[first + (uint32_t)__popcll(mask & lanemask_lt(lane))] = (uint32_t)f;
+  };
+  push(c > 1 && c <= (uint32_t)kHugeChunks, bigbins, nbig);
+  push(c > (uint32_t)kHugeChunks, hugebins, nhuge);
 }
 
 // Big bins: in-degree of every vertex of the bin within each chunk.
@@ -667,17 +680,19 @@ __global__ __launch_bounds__(WAVES *kWave) void k_big_count(FinalArgs a) {
 
 // Big bins, after k_big_count: per-vertex exclusive prefix over the bin's
 // chunks (in place) and the bin's CSC offsets.  One workgroup per big bin.
-template <int NT>
+// Bins of more than kHugeChunks chunks (a few hub regions) come in a second
+// launch with one thread per vertex and more rows in flight: their chains of
+// dependent round trips set the kernel's length.
+template <int NT, int B, bool HUGE>
 __global__ __launch_bounds__(NT) void k_big_scan(FinalArgs a) {
   __shared__ uint64_t s_tot[1 << kMaxFineBits];
   __shared__ uint64_t s_w64[NT / kWave + 1];
-  if ((int64_t)blockIdx.x >= (int64_t)*a.nbig) return;
-  const uint32_t f = a.bigbins[blockIdx.x];
+  if ((int64_t)blockIdx.x >= (int64_t)*(HUGE ? a.nhuge : a.nbig)) return;
+  const uint32_t f = (HUGE ? a.hugebins : a.bigbins)[blockIdx.x];
   const uint32_t nch = a.nch[f];
   const uint32_t first_item = a.item_base[f];
   const int tid = threadIdx.x;
   const int fw = 1 << a.fine_bits;
-  constexpr int B = 16;
   for (int v = tid; v < fw; v += NT) {
     uint64_t run = 0;
     for (uint32_t k0 = 0; k0 < nch; k0 += B) {
@@ -920,13 +935,17 @@ hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st) {
 
 hipError_t launch_item_map(const FinalArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_item_map, dim3((unsigned)((a.nbins + 255) / 256)), dim3(256), 0, st, a.nch, a.item_base,
-                     a.bin_start, a.nbins, final_tile_size(), a.item_desc, a.bigbins, a.nbig);
+                     a.bin_start, a.nbins, final_tile_size(), a.item_desc, a.bigbins, a.nbig, a.hugebins, a.nhuge);
   return hipGetLastError();
 }
 
-hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, hipStream_t st) {
+hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, int64_t max_huge, hipStream_t st) {
   if (max_big <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_big_scan<256>), dim3((unsigned)max_big), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_big_scan<256, 16, false>), dim3((unsigned)max_big), dim3(256), 0, st, a);
+  if (max_huge > 0) {
+    constexpr int NT = 1 << kMaxFineBits;  // one thread per vertex of the widest bin
+    hipLaunchKernelGGL((k_big_scan<NT, 32, true>), dim3((unsigned)max_huge), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 

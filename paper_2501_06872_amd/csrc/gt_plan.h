@@ -32,8 +32,8 @@ struct GraphPlan {
   size_t off_err, off_ticket, off_part, off_digit, off_dtot, off_bin, off_status, off_tsrc;
   size_t off_a_src, off_a_key, off_a_pay, off_a2_src, off_a2_key, off_a2_pay;
   size_t off_b_src, off_b_key, off_b_pay;
-  size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big;
-  int64_t max_big;
+  size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big, off_huge;
+  int64_t max_big, max_huge;
   int64_t max_items;
   // unordered strategies (GT_STRATEGY_HLH / GT_STRATEGY_ATOMIC)
   int strategy;

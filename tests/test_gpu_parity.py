@@ -142,6 +142,24 @@ def test_random_graphs_default_params(hip_device, n, avg, skew, payload):
     assert_parity(O, D, P, hip_device, f"random n={n} avg={avg} skew={skew}")
 
 
+def test_bins_of_many_chunks(hip_device):
+    # one bin of ~88 work items (the wider column-prefix launch for bins of
+    # more than 64 chunks), one of ~30 and many small ones
+    rng = np.random.default_rng(21)
+    n, m = 20_000, 1_200_000
+    src = np.sort(rng.integers(0, n, size=m))
+    D = rng.integers(0, n, size=m).astype(np.int32)
+    u = rng.random(m)
+    D[u < 0.6] = 3
+    hit = (u >= 0.6) & (u < 0.8)
+    D[hit] = rng.integers(512, 1024, size=int(hit.sum()))
+    order = np.lexsort((D, src))
+    src, D = src[order], D[order]
+    O = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int64)
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32)
+    assert_parity(O, D, P, hip_device, "bins of many chunks", policy=1, fine_bits=9, digit_bits=8, variant=1)
+
+
 @pytest.mark.parametrize("share", [1.0, 0.9, 0.3])
 def test_hub_rows(hip_device, share):
     # one destination takes `share` of a bin spanning many work items: rows of
