@@ -166,11 +166,12 @@ __device__ __forceinline__ void status_store(W *p, W v) {
 // Exclusive prefix of this tile's `count` over all earlier tiles of the same
 // column (`stride` = number of columns); publishes the aggregate, then the
 // inclusive prefix.  The predecessors are read kLookWin tiles per round trip,
-// starting with the immediate one: a tile's nearest inclusive predecessor is
-// usually a few dozen tiles back (a tile publishes its inclusive prefix only
-// after its own look-back), so reading the immediate predecessor alone first
-// would cost a round trip that almost never ends the walk.
-constexpr int kLookWin = 8;
+// starting with the immediate one (a tile publishes its inclusive prefix only
+// after its own look-back, so the immediate predecessor alone rarely ends the
+// walk).  Each status row a window reads is another tile's row of digit
+// words, mostly held in another XCD's L2; among windows of 4, 8 and 16 tiles
+// the partition passes ran fastest with 4.
+constexpr int kLookWin = 4;
 
 // First half: publish this tile's aggregate (tile 0: its inclusive prefix).
 template <typename W>
