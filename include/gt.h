@@ -26,14 +26,17 @@
  *
  * Streams: gt_transpose / gt_transpose_batched enqueue kernels on `stream`
  * and return without synchronising, so they may be captured into a HIP graph.
- * gt_plan synchronises `stream` once when its policy samples the graph.
+ * gt_plan with the HEURISTIC or FIXED policy does no device work and no
+ * synchronisation (it may be called while `stream` is being captured); the
+ * MLP policy, GT_FLAG_FEATURES and GT_STRATEGY_PROBE sample or time the
+ * graph on `stream` and synchronise it once.
  * A plan and a workspace must not be used by two streams at the same time.
  *
  * Errors: argument and size problems are reported synchronously by the
  * return code; nothing throws across this interface.  Conditions found on the
- * device (an invalid graph when validation is on) are written to a status
- * word in the workspace and read with gt_device_status() after the stream
- * has been synchronised.
+ * device (an invalid graph when validation is on, a count that does not add
+ * up) are written to a status word in the workspace and read with
+ * gt_plan_device_status() after the stream has been synchronised.
  */
 #ifndef GT_H
 #define GT_H
@@ -50,9 +53,18 @@ typedef enum {
   GT_ERR_INVALID_ARGUMENT = 1,   /* NULL pointer, negative size, n > 2^31-1, payload mismatch */
   GT_ERR_INVALID_GRAPH = 2,      /* device-detected: bad offsets or an index outside [0, n) */
   GT_ERR_WORKSPACE_TOO_SMALL = 3,
-  GT_ERR_UNSUPPORTED = 4,        /* a parameter outside the compiled kernel variants */
-  GT_ERR_HIP = 5                 /* a HIP runtime call failed */
+  GT_ERR_UNSUPPORTED = 4,        /* a parameter outside the compiled kernel variants, or m > 2^32 */
+  GT_ERR_HIP = 5,                /* a HIP runtime call failed */
+  GT_ERR_COUNTER_OVERFLOW = 6    /* device-detected: counts that do not add up to m (a wrapped counter) */
 } gt_status;
+
+/* Largest edge count accepted (GT_ERR_UNSUPPORTED above it): with m <= 2^32
+ * every 64-bit total and every 32-bit per-chunk prefix of one vertex's list
+ * is exact.  The device still checks that every pass's digit counts add up
+ * to m and every heavy bin's vertex counts to the bin's length; a mismatch
+ * (only a wrapped counter can cause one) is reported as
+ * GT_ERR_COUNTER_OVERFLOW by gt_plan_device_status(). */
+#define GT_MAX_EDGES 4294967296LL
 
 /* A CSR graph (input).  Device pointers; payload may be NULL. */
 typedef struct {
@@ -71,7 +83,7 @@ typedef struct {
 
 /* Policies for choosing the kernel parameters of a plan. */
 enum {
-  GT_POLICY_HEURISTIC = 0,  /* sizes and sampled degree features (default) */
+  GT_POLICY_HEURISTIC = 0,  /* from n and m alone (default): no device work while planning */
   GT_POLICY_FIXED = 1,      /* use fine_bits / digit_bits / variant as given */
   GT_POLICY_MLP = 2         /* learned choice from sampled features (falls back to HEURISTIC) */
 };
@@ -82,7 +94,7 @@ typedef struct {
   int32_t fine_bits;     /* log2 of the vertex range sorted in LDS by the last kernel (4..9) */
   int32_t digit_bits;    /* maximum digit width of one stable partition pass (4..10) */
   int32_t variant;       /* tile variant of the partition kernels (0 = auto, 1..N) */
-  int32_t validate;      /* 1: check offsets/indices on the device (status word) */
+  int32_t validate;      /* 1: also check the offsets on the device (indices are always checked) */
   uint64_t seed;         /* seed of the degree-sampling pass */
   const char *model_path;/* weights of the learned policy (GT_POLICY_MLP) */
   int32_t flags;         /* GT_FLAG_* */
@@ -112,8 +124,11 @@ typedef struct {
 enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2, GT_STRATEGY_PROBE = 3 };
 
 /* Flags.  GT_FLAG_WIDE_STATUS forces the 64-bit look-back words that graphs
- * with m >= 2^31 use, so that path can be tested on small graphs. */
-enum { GT_FLAG_WIDE_STATUS = 1 };
+ * with m >= 2^31 use, so that path can be tested on small graphs.
+ * GT_FLAG_FEATURES makes gt_plan sample every graph and keep its feature
+ * vector (gt_plan_features) whatever the policy; it then needs the sampling
+ * scratch (gt_plan_scratch_size) and synchronises the stream. */
+enum { GT_FLAG_WIDE_STATUS = 1, GT_FLAG_FEATURES = 2 };
 
 typedef struct gt_plan_st *gt_plan_t;
 
@@ -122,8 +137,8 @@ typedef struct gt_plan_st *gt_plan_t;
 gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out);
 
 /* Bytes of workspace gt_plan needs for `count` graphs: the degree-sampling
- * scratch and the learned policy's inputs (the HEURISTIC and MLP policies;
- * the FIXED policy touches no workspace while planning). */
+ * scratch and the learned policy's inputs (the MLP policy and
+ * GT_FLAG_FEATURES; HEURISTIC and FIXED plans touch no workspace). */
 gt_status gt_plan_scratch_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out);
 
 /* Bytes of workspace gt_transpose / gt_transpose_batched need with the
@@ -139,13 +154,14 @@ gt_status gt_plan_workspace_size(gt_plan_t plan, size_t *bytes_out);
  *               read by the sampling kernels during this call only)
  *   opt         options, or NULL for the defaults
  *   workspace   device buffer of at least gt_plan_scratch_size() bytes for
- *               the HEURISTIC and MLP policies (may be NULL for FIXED);
- *               clobbered
+ *               the MLP policy and GT_FLAG_FEATURES (may be NULL for
+ *               HEURISTIC and FIXED); clobbered
  *   stream      HIP stream (hipStream_t) of the sampling kernels; the call
- *               synchronises it once when the policy samples
+ *               synchronises it once when it samples (MLP, GT_FLAG_FEATURES,
+ *               GT_STRATEGY_PROBE), and does not touch it otherwise
  *   plan_out    receives the plan (host memory only; gt_plan_destroy)
  * Errors: GT_ERR_INVALID_ARGUMENT (NULL pointer, count <= 0, n < 0, m < 0,
- * n > 2^31 - 1), GT_ERR_UNSUPPORTED (an option out of range),
+ * n > 2^31 - 1), GT_ERR_UNSUPPORTED (an option out of range, m > 2^32),
  * GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_HIP. */
 gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
                   size_t workspace_bytes, void *stream, gt_plan_t *plan_out);
@@ -163,10 +179,12 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
  *   stream      HIP stream; the call only enqueues kernels (no host
  *               synchronisation, capturable into a HIP graph)
  * Errors: GT_ERR_INVALID_ARGUMENT (NULL pointers, sizes other than the
- * plan's), GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_HIP (a launch failed).  With
- * opt->validate an invalid graph is reported by gt_device_status() after the
- * stream has completed; without it the output of an invalid graph is
- * undefined (but every kernel stays inside its buffers). */
+ * plan's), GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_HIP (a launch failed).  An
+ * index outside [0, n) is always reported by gt_plan_device_status() after
+ * the stream has completed (GT_ERR_INVALID_GRAPH); opt->validate adds the
+ * check of the offsets.  The output of an invalid graph is undefined, but
+ * every kernel stays inside its buffers: an edge whose destination does not
+ * exist is never written outside the output arrays. */
 gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *workspace,
                        size_t workspace_bytes, void *stream);
 
@@ -179,9 +197,17 @@ gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *w
 gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
                                void *workspace, size_t workspace_bytes, void *stream);
 
-/* After the stream has been synchronised: GT_OK, or GT_ERR_INVALID_GRAPH if
- * validation found a bad input (offsets not nondecreasing from 0 to m, or an
- * index outside [0, n)).  Reads 4 bytes of the workspace (device memory). */
+/* After the stream has been synchronised: the device-detected status of the
+ * last transposition run with this plan in `workspace`.  GT_OK;
+ * GT_ERR_INVALID_GRAPH if an index lies outside [0, n) or (with validation)
+ * the offsets are not nondecreasing from 0 to m; GT_ERR_COUNTER_OVERFLOW if
+ * a count did not add up (see GT_MAX_EDGES).  Reads 4 bytes of the workspace
+ * with a blocking copy.  Errors: GT_ERR_INVALID_ARGUMENT (NULL plan or
+ * workspace), GT_ERR_HIP. */
+gt_status gt_plan_device_status(gt_plan_t plan, const void *workspace);
+
+/* The same status read without a plan (the status word is byte 0 of any
+ * workspace the library has used). */
 gt_status gt_device_status(const void *workspace);
 
 /* Parameters a plan selected for graph `i` (for reporting and tests): fine

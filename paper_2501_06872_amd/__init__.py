@@ -19,8 +19,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgt.so")
 
-GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP = \
-    range(6)
+(GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP,
+ GT_ERR_COUNTER_OVERFLOW) = range(7)
+MAX_EDGES = 1 << 32
 POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
 # STABLE: every CSC list in CSR edge order.  HLH / ATOMIC: the paper's methods,
 # list order left to the atomics (offsets and list contents exact).
@@ -28,7 +29,7 @@ STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
-           "gt_transpose_batched", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
+           "gt_transpose_batched", "gt_plan_device_status", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
            "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
@@ -76,6 +77,7 @@ def lib():
         L.gt_transpose.argtypes = [vp, P(CSR), P(CSC), vp, sz, vp]
         L.gt_transpose_batched.argtypes = [vp, i32, P(CSR), P(CSC), vp, sz, vp]
         L.gt_device_status.argtypes = [vp]
+        L.gt_plan_device_status.argtypes = [vp, vp]
         L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
         L.gt_plan_strategy.argtypes = [vp, i32, P(i32)]
         L.gt_plan_packed.argtypes = [vp, i32, P(i32)]
@@ -135,7 +137,7 @@ def _check_inputs(offsets, indices, payload):
             raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
 
 
-FLAG_WIDE_STATUS = 1
+FLAG_WIDE_STATUS, FLAG_FEATURES = 1, 2
 
 
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
@@ -266,7 +268,7 @@ class Plan:
 
     def device_status(self):
         torch.cuda.current_stream(self.device).synchronize()
-        return lib().gt_device_status(self.workspace.data_ptr())
+        return lib().gt_plan_device_status(self.handle, self.workspace.data_ptr())
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -32,8 +32,23 @@ bool valid_csr_args(const gt_csr_t &g) {
   if (g.n < 0 || g.m < 0 || g.n > INT32_MAX) return false;
   if (g.offsets == nullptr) return false;
   if (g.m > 0 && g.indices == nullptr) return false;
-  if (g.m >= (int64_t(1) << 40)) return false;
   return true;
+}
+
+// Argument status of one graph: the descriptor itself, then the size limit
+// (m <= 2^32 keeps every per-vertex chunk prefix of a big bin in 32 bits).
+gt_status csr_args_status(const gt_csr_t &g) {
+  if (!valid_csr_args(g)) return GT_ERR_INVALID_ARGUMENT;
+  if (g.m > kMaxEdges) return GT_ERR_UNSUPPORTED;
+  return GT_OK;
+}
+
+gt_status graphs_args_status(const gt_csr_t *graphs, int32_t count) {
+  for (int32_t i = 0; i < count; ++i) {
+    const gt_status s = csr_args_status(graphs[i]);
+    if (s != GT_OK) return s;
+  }
+  return GT_OK;
 }
 
 }  // namespace
@@ -227,7 +242,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   const int hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, (p.m + 4095) / 4096));
   GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, hist_blocks, part, err, st));
   GT_TIMED("k_digit_scan", launch_digit_scan(part, hist_blocks, h, reinterpret_cast<uint64_t *>(ws + p.off_dtot),
-                                             digit, bins, p.nbins_total, p.m, st));
+                                             digit, bins, p.nbins_total, p.m, err, st));
   GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
 
   const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
@@ -296,6 +311,7 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   f.nbig = f.total_items + 2;
   f.hugebins = reinterpret_cast<uint32_t *>(ws + p.off_huge);
   f.nhuge = f.total_items + 3;
+  f.err = err;
   uint32_t *sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
   const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
   GT_TIMED("k_bin_items", launch_bin_items(f, st));
@@ -428,17 +444,18 @@ const char *gt_status_string(gt_status s) {
     case GT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case GT_ERR_UNSUPPORTED: return "unsupported parameters";
     case GT_ERR_HIP: return "HIP runtime error";
+    case GT_ERR_COUNTER_OVERFLOW: return "counter overflow";
   }
   return "unknown status";
 }
 
 gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out) {
   if (graphs == nullptr || count <= 0 || bytes_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  const gt_status as = graphs_args_status(graphs, count);
+  if (as != GT_OK) return as;
   size_t total = 0;
-  for (int32_t i = 0; i < count; ++i) {
-    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+  for (int32_t i = 0; i < count; ++i)
     total += align_up(graph_workspace_bound(graphs[i].n, graphs[i].m, graphs[i].payload != nullptr));
-  }
   total += kAlign;  // status word
   total += align_up(plan_scratch_bytes(graphs, count));
   *bytes_out = total;
@@ -447,8 +464,8 @@ gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes
 
 gt_status gt_plan_scratch_size(const gt_csr_t *graphs, int32_t count, size_t *bytes_out) {
   if (graphs == nullptr || count <= 0 || bytes_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
-  for (int32_t i = 0; i < count; ++i)
-    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+  const gt_status as = graphs_args_status(graphs, count);
+  if (as != GT_OK) return as;
   *bytes_out = align_up(plan_scratch_bytes(graphs, count)) + kAlign;
   return GT_OK;
 }
@@ -462,8 +479,8 @@ gt_status gt_plan_workspace_size(gt_plan_t plan, size_t *bytes_out) {
 gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt, void *workspace,
                   size_t workspace_bytes, void *stream, gt_plan_t *plan_out) {
   if (graphs == nullptr || count <= 0 || plan_out == nullptr) return GT_ERR_INVALID_ARGUMENT;
-  for (int32_t i = 0; i < count; ++i)
-    if (!valid_csr_args(graphs[i])) return GT_ERR_INVALID_ARGUMENT;
+  const gt_status as = graphs_args_status(graphs, count);
+  if (as != GT_OK) return as;
   gt_options_t o{};
   if (opt) o = *opt;
   if (o.policy < GT_POLICY_HEURISTIC || o.policy > GT_POLICY_MLP) return GT_ERR_INVALID_ARGUMENT;
@@ -499,7 +516,8 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
 
 static gt_status check_io(const GraphPlan &p, const gt_csr_t *g, const gt_csc_t *out) {
   if (g == nullptr || out == nullptr) return GT_ERR_INVALID_ARGUMENT;
-  if (!valid_csr_args(*g)) return GT_ERR_INVALID_ARGUMENT;
+  const gt_status as = csr_args_status(*g);
+  if (as != GT_OK) return as;
   if (g->n != p.n || g->m != p.m || (g->payload != nullptr) != p.pay) return GT_ERR_INVALID_ARGUMENT;
   if (out->offsets == nullptr || (p.m > 0 && out->indices == nullptr)) return GT_ERR_INVALID_ARGUMENT;
   if ((out->payload != nullptr) != p.pay) return GT_ERR_INVALID_ARGUMENT;
@@ -533,7 +551,14 @@ gt_status gt_device_status(const void *workspace) {
   if (workspace == nullptr) return GT_ERR_INVALID_ARGUMENT;
   uint32_t err = 0;
   if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return GT_ERR_HIP;
-  return err ? GT_ERR_INVALID_GRAPH : GT_OK;
+  if (err & (kErrBadIndex | kErrBadOffsets)) return GT_ERR_INVALID_GRAPH;
+  if (err & kErrOverflow) return GT_ERR_COUNTER_OVERFLOW;
+  return GT_OK;
+}
+
+gt_status gt_plan_device_status(gt_plan_t plan, const void *workspace) {
+  if (plan == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  return gt_device_status(workspace);
 }
 
 gt_status gt_plan_params(gt_plan_t plan, int32_t i, int32_t *fine_bits, int32_t *digit_bits, int32_t *passes,

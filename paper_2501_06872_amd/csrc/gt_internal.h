@@ -10,8 +10,17 @@ constexpr int kMaxRadix = 1024;   // digit width <= 10 bits
 constexpr int kMaxFineBits = 9;   // bins of <= 512 destinations in k_final
 constexpr int kHistBlocks = 1280;
 
+// Largest edge count a plan accepts: every per-vertex prefix over the chunks
+// of a big bin (k_big_scan) stays below 2^32.
+constexpr int64_t kMaxEdges = int64_t(1) << 32;
+
+// Bits of the device status word (byte 0 of the workspace).
 constexpr uint32_t kErrBadIndex = 1u;
 constexpr uint32_t kErrBadOffsets = 2u;
+// A count that does not add up: the digit totals of a pass differ from m, or
+// the per-vertex counts of a big bin from the bin's length (only a counter
+// that wrapped can cause either).
+constexpr uint32_t kErrOverflow = 4u;
 
 struct HistArgs {
   int passes;
@@ -78,6 +87,7 @@ struct FinalArgs {
   uint32_t *nbig;         // device scalar
   uint32_t *hugebins;     // [max huge bins] bins split into more than kHugeChunks chunks
   uint32_t *nhuge;        // device scalar
+  uint32_t *err;          // device status word
 };
 
 int64_t lsd_tile_size(int variant);
@@ -106,6 +116,6 @@ hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h
                        uint32_t *err, hipStream_t st);
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
                              uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
-                             hipStream_t st);
+                             uint32_t *err, hipStream_t st);
 
 }  // namespace gt

@@ -187,14 +187,15 @@ __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict
 // bin start.
 __global__ __launch_bounds__(1024) void k_digit_scan(const uint64_t *__restrict__ totals, HistArgs h,
                                                      uint64_t *digit_start, uint64_t *bin_start,
-                                                     int64_t nbins_total, int64_t m) {
+                                                     int64_t nbins_total, int64_t m, uint32_t *err) {
   __shared__ uint64_t s_tot[kMaxRadix];
   __shared__ uint64_t s_wsum[1024 / kWave + 1];
   const int p = blockIdx.x, tid = threadIdx.x;
   const int radix = 1 << h.bits[p];
   for (int d = tid; d < radix; d += blockDim.x) s_tot[d] = totals[p * kMaxRadix + d];
   __syncthreads();
-  block_excl_scan<1024, uint64_t>(s_tot, radix, s_wsum);
+  const uint64_t sum = block_excl_scan<1024, uint64_t>(s_tot, radix, s_wsum);
+  if (tid == 0 && sum != (uint64_t)m) atomicOr(err, kErrOverflow);  // every edge has one digit per pass
   for (int d = tid; d < radix; d += blockDim.x) digit_start[p * (kMaxRadix + 1) + d] = s_tot[d];
   if (tid == 0) digit_start[p * (kMaxRadix + 1) + radix] = (uint64_t)m;
   if (p == 0 && tid == 0) bin_start[nbins_total] = (uint64_t)m;
@@ -709,8 +710,9 @@ __global__ __launch_bounds__(NT) void k_big_scan(FinalArgs a) {
     s_tot[v] = run;
   }
   __syncthreads();
-  block_excl_scan<NT, uint64_t>(s_tot, fw, s_w64);
+  const uint64_t bin_total = block_excl_scan<NT, uint64_t>(s_tot, fw, s_w64);
   const uint64_t bs = a.bin_start[f];
+  if (tid == 0 && bs + bin_total != a.bin_start[f + 1]) atomicOr(a.err, kErrOverflow);
   const int64_t v0 = (int64_t)f << a.fine_bits;
   for (int v = tid; v < fw; v += NT)
     if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_tot[v]);
@@ -753,7 +755,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   lds_zero16(s_stage, 2 * WAVES * FW * 4, tid, NT);
   if (!whole) {
     const uint32_t *row = a.cntab + (uint64_t)item * fw;
-    for (int v = tid; v < fw; v += NT) s_cur[v] = (uint64_t)a.T[v0 + v < a.n ? v0 + v : a.n] + row[v];
+    for (int v = tid; v < fw; v += NT) s_cur[v] = v0 + v < a.n ? (uint64_t)a.T[v0 + v] + row[v] : 0ull;
   }
   __syncthreads();
   uint32_t key[ITEMS], lpos[ITEMS];
@@ -827,6 +829,17 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
     const uint32_t v = (vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
     return s_cur[v] + (uint64_t)i;
   };
+  // Only an invalid graph has a destination v >= n (in the last bin, below
+  // the next power of two).  A whole bin keeps such edges inside its own
+  // slots; in a chunk of a big bin they have no cursor (T[v] does not exist)
+  // and are dropped, so no write leaves [0, m).  k_hist has already flagged
+  // the graph as invalid.
+  const int64_t nvalid = a.n - v0;  // vertices of the bin that exist
+  auto slot_ok = [&](int k, int i) -> bool {
+    if (i >= cnt) return false;
+    if (whole) return true;
+    return (int64_t)((vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu) < nvalid;
+  };
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
@@ -835,7 +848,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const int i = k * NT + tid;
-    if (i < cnt) a.S[gpos_of(k, i)] = (int32_t)s_stage[i];
+    if (slot_ok(k, i)) a.S[gpos_of(k, i)] = (int32_t)s_stage[i];
   }
   if (PAY) {
     uint32_t pay[ITEMS];
@@ -849,7 +862,7 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int i = k * NT + tid;
-      if (i < cnt) a.Q[gpos_of(k, i)] = s_stage[i];
+      if (slot_ok(k, i)) a.Q[gpos_of(k, i)] = s_stage[i];
     }
   }
 }
@@ -1010,10 +1023,10 @@ hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h
 
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
                              uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
-                             hipStream_t st) {
+                             uint32_t *err, hipStream_t st) {
   hipLaunchKernelGGL(k_digit_reduce, dim3(h.passes * (kMaxRadix / 64)), dim3(256), 0, st, part, nblocks, h, totals);
   hipLaunchKernelGGL(k_digit_scan, dim3(h.passes), dim3(1024), 0, st, totals, h, digit_start, bin_start,
-                     nbins_total, m);
+                     nbins_total, m, err);
   return hipGetLastError();
 }
 

@@ -28,9 +28,9 @@ size_t plan_scratch_bytes(const gt_csr_t *graphs, int32_t count) {
   return total;
 }
 
-// Heuristic: a k_final bin should hold about one 8K-edge tile, so
-// fine_bits ~ log2(8192 / average in-degree); digits of up to 10 bits; the
-// 8-wave x 16-edge tile.
+// Heuristic (sizes only): a k_final bin should hold about one 8K-edge tile,
+// so fine_bits ~ log2(8192 / average in-degree); digits of up to 10 bits;
+// the 8-wave x 16-edge tile.
 static void heuristic(GraphPlan &p) {
   const double avg = p.n > 0 ? (double)p.m / (double)p.n : 1.0;
   int fb = (int)lround(log2(8192.0 / std::max(avg, 1.0)));
@@ -156,7 +156,9 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
       if (opt.variant) p.variant = opt.variant;
     }
   }
-  if (opt.policy == GT_POLICY_HEURISTIC || opt.policy == GT_POLICY_MLP) {
+  // HEURISTIC and FIXED choose from the sizes alone: no device work and no
+  // synchronisation unless features were asked for.
+  if (opt.policy == GT_POLICY_MLP || (opt.flags & GT_FLAG_FEATURES)) {
     char *base = scratch_base(graphs, count, workspace, workspace_bytes);
     if (base == nullptr) return GT_ERR_WORKSPACE_TOO_SMALL;
     gt_status s = sample_features(plan, graphs, count, opt.seed ? opt.seed : 0x5eedull, base, st);

@@ -74,7 +74,7 @@ def collect(specs, dev, reps, seed=77, verbose=False):
              torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None)
         if verbose:
             log(f"  [graph {k}] n={O.size - 1} m={D.size} spec={specs[k]}")
-        feats = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=seed)).features()
+        feats = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=seed, flags=gt.FLAG_FEATURES)).features()
         ms, _ = gt.autotune(*g, reps=reps)
         X.append(feats)
         Tm.append(ms)

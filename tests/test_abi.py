@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("gt_plan", "gt_transpose", "gt_transpose_batched", "gt_workspace_size", "gt_plan_destroy",
-              "gt_status_string", "gt_device_status"):
+              "gt_status_string", "gt_device_status", "gt_plan_device_status"):
         assert f in names
 
 
@@ -51,6 +51,34 @@ def test_status_strings_and_argument_errors_without_gpu():
     assert L.gt_plan(ctypes.byref(ok), 1, ctypes.byref(opts), None, 0, None, ctypes.byref(h)) == \
         gt.GT_ERR_UNSUPPORTED
     assert L.gt_transpose(None, None, None, None, 0, None) == gt.GT_ERR_INVALID_ARGUMENT
+    # more than 2^32 edges: refused before any device work
+    huge = gt.CSR(1 << 28, (1 << 32) + 1, 1, 1, None)
+    assert L.gt_workspace_size(ctypes.byref(huge), 1, ctypes.byref(size)) == gt.GT_ERR_UNSUPPORTED
+    assert L.gt_plan(ctypes.byref(huge), 1, None, None, 0, None, ctypes.byref(h)) == gt.GT_ERR_UNSUPPORTED
+    at_limit = gt.CSR(1 << 28, 1 << 32, 1, 1, None)
+    assert L.gt_workspace_size(ctypes.byref(at_limit), 1, ctypes.byref(size)) == gt.GT_OK
+    assert gt.status_string(gt.GT_ERR_COUNTER_OVERFLOW) == "counter overflow"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgt.so not built")
+def test_heuristic_and_fixed_plans_do_no_device_work():
+    """There is no GPU in this process: a plan that touched the device
+    (sampling, a synchronisation) would fail.  HEURISTIC (the default, no
+    options) and FIXED plans succeed with no workspace and no stream."""
+    import paper_2501_06872_amd as gt
+    L = gt.lib()
+    g = gt.CSR(1 << 26, 1 << 30, 1, 1, None)
+    for opts in (None, gt.make_options(policy=gt.POLICY_HEURISTIC),
+                 gt.make_options(policy=gt.POLICY_FIXED, fine_bits=8, digit_bits=9)):
+        h = ctypes.c_void_p()
+        rc = L.gt_plan(ctypes.byref(g), 1, ctypes.byref(opts) if opts is not None else None, None, 0, None,
+                       ctypes.byref(h))
+        assert rc == gt.GT_OK
+        out = [ctypes.c_int32() for _ in range(4)]
+        assert L.gt_plan_params(h, 0, *[ctypes.byref(x) for x in out]) == gt.GT_OK
+        assert out[2].value == 2  # two partition passes at 2^26 vertices
+        assert L.gt_plan_device_status(None, None) == gt.GT_ERR_INVALID_ARGUMENT
+        assert L.gt_plan_destroy(h) == gt.GT_OK
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libgt.so not built")

@@ -329,3 +329,52 @@ def test_invalid_graph_reported(hip_device):
     say("[case] invalid offsets, validate=1")
     _, _, _, st, _ = gpu_transpose(O2, D2, None, hip_device, validate=True)
     assert st == gt.GT_ERR_INVALID_GRAPH
+
+
+@pytest.mark.parametrize("payload", [False, True])
+@pytest.mark.parametrize("validate", [False, True])
+def test_invalid_ids_in_a_big_last_bin_stay_in_bounds(hip_device, payload, validate):
+    """Destinations in [n, 2^ceil(log2 n)) and negative ones (whose masked
+    digits alias into that range) inside a last bin longer than one k_final
+    item: the graph is reported invalid and no write leaves the outputs
+    (canary words after S, Q and T stay untouched)."""
+    import paper_2501_06872_amd as gt
+    n, m = 1000, 16000
+    rng = np.random.default_rng(3)
+    O = np.linspace(0, m, n + 1).astype(np.int64)
+    cases = (("heuristic plan (one bin of 512..1023)", rng.integers(512, 1024, size=m), {}),
+             ("fixed plan, 16-vertex bins", rng.integers(992, 1024, size=m),
+              dict(policy=gt.POLICY_FIXED, fine_bits=4, digit_bits=3)))
+    for label, D, opt in cases:
+        D = D.astype(np.int32)
+        D[::97] = -1
+        for u in range(n):
+            D[O[u]:O[u + 1]].sort()
+        assert np.count_nonzero(D >= n) + np.count_nonzero(D < 0) > 8192 // 16
+        P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
+        say(f"[case] invalid ids in a big last bin: {label}, payload={payload}, validate={validate}")
+        O_t, D_t, P_t = to_dev(O, D, P, hip_device)
+        canary = 0x5A5A5A5A
+        pad = 4096
+        T_big = torch.full((n + 1 + pad,), canary, dtype=torch.int64, device=hip_device)
+        S_big = torch.full((m + pad,), canary, dtype=torch.int32, device=hip_device)
+        Q_big = torch.full((m + pad,), canary, dtype=torch.int32, device=hip_device) if payload else None
+        out = (T_big[:n + 1], S_big[:m], Q_big[:m] if payload else None)
+        plan = gt.Plan([(O_t, D_t, P_t)], gt.make_options(validate=validate, **opt))
+        say("  params", plan.params())
+        plan.run(O_t, D_t, P_t, out=out)
+        torch.cuda.synchronize()
+        assert plan.device_status() == gt.GT_ERR_INVALID_GRAPH
+        assert bool((T_big[n + 1:] == canary).all()), "write past T"
+        assert bool((S_big[m:] == canary).all()), "write past S"
+        if payload:
+            assert bool((Q_big[m:] == canary).all()), "write past Q"
+
+
+def test_counter_check_quiet_on_valid_graphs(hip_device):
+    # the digit-total and big-bin count checks raise no overflow on valid input
+    import paper_2501_06872_amd as gt
+    O, D, P = gen.rmat(18, 16, seed=5, permute=False)
+    say("[case] counter checks on rmat18 (natural order: many big bins)")
+    T, S, Q, st, params = gpu_transpose(O, D, P, hip_device)
+    assert st == gt.GT_OK

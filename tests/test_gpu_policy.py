@@ -48,7 +48,7 @@ def test_features_match_oracle(hip_device, name):
     O, D, P = graphs()[name]
     say(f"[case] features {name} n={O.size - 1} m={D.size}")
     g = dev_graph(O, D, P, hip_device)
-    plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77))
+    plan = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77, flags=gt.FLAG_FEATURES))
     got = np.array(plan.features(), dtype=np.float32)
     ref = OF.features(O, D, P is not None, seed=77)
     assert got.shape == ref.shape
@@ -108,7 +108,7 @@ def test_mlp_policy_picks_argmin_and_falls_back(hip_device):
         # features outside the training range keep the heuristic choice
         mlp_model.save(path, p, np.full(16, 5.0), np.full(16, 5.0))
         plan2 = gt.Plan([g], gt.make_options(policy=gt.POLICY_MLP, seed=77, model_path=path))
-        plan3 = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77))
+        plan3 = gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77, flags=gt.FLAG_FEATURES))
         assert plan2.params() == plan3.params()
 
 
@@ -145,7 +145,7 @@ def test_committed_model_drives_the_plan(hip_device):
             ok = [(gt.config(c)["fine_bits"], resolved_variant(gt.config(c), got)) for c in near]
             assert (got["fine_bits"], got["variant"]) in ok
         else:
-            assert plan.params() == gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77)).params()
+            assert plan.params() == gt.Plan([g], gt.make_options(policy=gt.POLICY_HEURISTIC, seed=77, flags=gt.FLAG_FEATURES)).params()
         T, S, Q = plan.run(*g)
         torch.cuda.synchronize()
         rT, rS, rQ = oracle.transpose(O, D, P)

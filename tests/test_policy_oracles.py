@@ -108,3 +108,60 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([0.3, -4.0, 1e-3])
     p1, _, _ = M.adam_step(p, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     assert np.allclose(p1, p - 0.01 * np.sign(g), atol=1e-7)
+
+
+def mixed_frequency_graph():
+    """A graph small enough (m <= 4096) that the sample is every edge once:
+    s = m, so each stratum is one position.  Destinations, by construction:
+      5 hubs 70000..70004, 40 in-edges each from sources 0..39   (bucket 5)
+      10 vertices 1000..1009, 10 in-edges each from v+1..v+10     (bucket 3)
+      1500 vertices 20000..21499, from v+200 and from v+60000     (bucket 1)
+      500 vertices 90000..90499, one in-edge each from v-80000    (bucket 0)
+    n = 100000, m = 200 + 100 + 3000 + 500 = 3800."""
+    pairs = []
+    for h in range(5):
+        pairs += [(u, 70000 + h) for u in range(40)]
+    for k in range(10):
+        pairs += [(1000 + k + j, 1000 + k) for j in range(1, 11)]
+    for k in range(1500):
+        pairs += [(20000 + k + 200, 20000 + k), (20000 + k + 60000, 20000 + k)]
+    for k in range(500):
+        pairs += [(90000 + k - 80000, 90000 + k)]
+    n = 100000
+    pairs.sort(key=lambda p: p[0])  # stable: CSR order by source
+    src = np.array([p[0] for p in pairs], dtype=np.int64)
+    D = np.array([p[1] for p in pairs], dtype=np.int32)
+    O = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int64)
+    return O, D, src
+
+
+def test_features_of_a_mixed_frequency_graph_by_hand():
+    """Every feature computed by hand from the construction above, including
+    the share of a partly taken frequency bucket in the coverage estimate."""
+    O, D, src = mixed_frequency_graph()
+    n, m = O.size - 1, D.size
+    assert m == 3800 and F.sample_count(n, m) == m
+    assert np.array_equal(F.sample_positions(n, m, seed=11).astype(np.int64), np.arange(m))
+    f = F.features(O, D, True, seed=11).astype(np.float64)
+    s = 3800.0
+    assert np.isclose(f[0], np.log2(100001) / 32)
+    assert np.isclose(f[1], np.log2(3801) / 40)                  # log m
+    assert np.isclose(f[2], np.log2(3800 / 100000 + 1) / 8)      # edge factor
+    assert f[3] == 1.0
+    # edges into destinations sampled at least 2, 4, 16, 64 times
+    assert np.isclose(f[4], (200 + 100 + 3000) / s)
+    assert np.isclose(f[5], (200 + 100) / s)
+    assert np.isclose(f[6], 200 / s)
+    assert f[7] == 0.0
+    # coverage of the 1024 most frequent: the 5 hubs (200), the 10 (100),
+    # then 1009 of the 1500 twice-sampled vertices at 2 each (partial bucket)
+    assert np.isclose(f[8], (200 + 100 + 1009 * 2) / s)
+    assert np.isclose(f[9], 1.0) and np.isclose(f[10], 1.0)      # 2015 keys < 2^14
+    dist_sum = (sum(70000 + h - u for h in range(5) for u in range(40)) + 10 * sum(range(1, 11))
+                + 1500 * (200 + 60000) + 500 * 80000)
+    assert np.isclose(f[11], dist_sum / (s * n), rtol=1e-6)
+    assert np.isclose(f[12], (100 + 1500) / s)                   # |dst - src| < 256
+    assert np.isclose(f[13], (100 + 1500 + 1500) / s)            # |dst - src| < 65536
+    assert f[14] == 0.0                                           # no 256-vertex bin near 8K edges
+    assert np.isclose(f[15], (5 + 10 + 1500 + 500) / s)          # distinct destinations
+
