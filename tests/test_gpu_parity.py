@@ -343,14 +343,18 @@ def test_invalid_ids_in_a_big_last_bin_stay_in_bounds(hip_device, payload, valid
     rng = np.random.default_rng(3)
     O = np.linspace(0, m, n + 1).astype(np.int64)
     cases = (("heuristic plan (one bin of 512..1023)", rng.integers(512, 1024, size=m), {}),
-             ("fixed plan, 16-vertex bins", rng.integers(992, 1024, size=m),
-              dict(policy=gt.POLICY_FIXED, fine_bits=4, digit_bits=3)))
+             ("fixed plan, 16-vertex bins", rng.integers(1000, 1024, size=m),
+              dict(policy=gt.POLICY_FIXED, fine_bits=4, digit_bits=4)))
     for label, D, opt in cases:
         D = D.astype(np.int32)
         D[::97] = -1
         for u in range(n):
             D[O[u]:O[u + 1]].sort()
         assert np.count_nonzero(D >= n) + np.count_nonzero(D < 0) > 8192 // 16
+        # the premise: the last bin (digits masked to 10 bits, as the
+        # kernels see them) is longer than one 8192-edge k_final item
+        fb = opt.get("fine_bits", 9)
+        assert np.bincount((D.astype(np.int64) & 1023) >> fb).max() > 8192
         P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32) if payload else None
         say(f"[case] invalid ids in a big last bin: {label}, payload={payload}, validate={validate}")
         O_t, D_t, P_t = to_dev(O, D, P, hip_device)
