@@ -197,6 +197,36 @@ gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *w
 gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
                                void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- For callers that cannot allocate device memory (code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc):
+ * gt_transpose with the library's own scratch instead of a workspace.
+ * The scratch is one static device array of GT_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the first call on that GPU until the process ends; the call
+ * itself allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine) and does not synchronise.  Every call on one GPU shares that
+ * GPU's scratch, so calls that overlap on one GPU (two streams, two host
+ * threads) race: the caller serialises them.  The scratch keeps the last
+ * call's contents; everything that must start at zero is cleared by the
+ * call's own kernels.
+ *   plan        built with count == 1 (any policy and strategy) for a graph
+ *               of the same n, m and payload presence; its workspace need
+ *               (gt_plan_workspace_size) must be at most
+ *               GT_NOALLOC_SCRATCH_BYTES
+ *   g, out      as gt_transpose
+ *   status_out  NULL, or a device pointer to one uint32 that receives the
+ *               device-detected status word when the stream reaches the end
+ *               of the call: 0 = GT_OK, else bit 0 or 1 = GT_ERR_INVALID_GRAPH,
+ *               bit 2 = GT_ERR_COUNTER_OVERFLOW (the conditions of
+ *               gt_plan_device_status)
+ *   stream      HIP stream of the current device (the scratch is that
+ *               device's copy)
+ * Errors: as gt_transpose; GT_ERR_WORKSPACE_TOO_SMALL when the plan needs
+ * more than GT_NOALLOC_SCRATCH_BYTES; GT_ERR_INVALID_ARGUMENT when `stream`
+ * belongs to another device than the current one. */
+#define GT_NOALLOC_SCRATCH_BYTES (64u << 20)
+gt_status gt_transpose_noalloc(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, uint32_t *status_out,
+                               void *stream);
+
 /* After the stream has been synchronised: the device-detected status of the
  * last transposition run with this plan in `workspace`.  GT_OK;
  * GT_ERR_INVALID_GRAPH if an index lies outside [0, n) or (with validation)

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 (GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP,
  GT_ERR_COUNTER_OVERFLOW) = range(7)
 MAX_EDGES = 1 << 32
+NOALLOC_SCRATCH_BYTES = 64 << 20  # the library's own scratch per GPU (gt_transpose_noalloc)
 POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
 # STABLE: every CSC list in CSR edge order.  HLH / ATOMIC: the paper's methods,
 # list order left to the atomics (offsets and list contents exact).
@@ -29,7 +30,7 @@ STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
-           "gt_transpose_batched", "gt_plan_device_status", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
+           "gt_transpose_batched", "gt_transpose_noalloc", "gt_plan_device_status", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
            "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
@@ -76,6 +77,7 @@ def lib():
         L.gt_plan.argtypes = [P(CSR), i32, P(Options), vp, sz, vp, P(vp)]
         L.gt_transpose.argtypes = [vp, P(CSR), P(CSC), vp, sz, vp]
         L.gt_transpose_batched.argtypes = [vp, i32, P(CSR), P(CSC), vp, sz, vp]
+        L.gt_transpose_noalloc.argtypes = [vp, P(CSR), P(CSC), vp, vp]
         L.gt_device_status.argtypes = [vp]
         L.gt_plan_device_status.argtypes = [vp, vp]
         L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
@@ -225,6 +227,21 @@ class Plan:
                 (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
         _check(lib().gt_transpose(self.handle, ctypes.byref(g), ctypes.byref(o), self.workspace.data_ptr(),
                                   self.workspace.numel(), _stream_ptr(self.device)), "gt_transpose")
+        return T, S, Q
+
+    def run_noalloc(self, offsets, indices, payload, out, status=None):
+        """gt_transpose_noalloc: the library's static scratch instead of the
+        plan's workspace.  ``out`` = caller-allocated (T, S, Q); ``status``
+        None or a 1-element 32-bit GPU tensor that receives the device
+        status word."""
+        _check_inputs(offsets, indices, payload)
+        T, S, Q = out
+        g = _csr(offsets, indices, payload)
+        o = CSC(T.data_ptr(), S.data_ptr() if S.numel() else None,
+                (Q.data_ptr() if Q.numel() else 1) if Q is not None else None)
+        st = status.data_ptr() if status is not None else None
+        _check(lib().gt_transpose_noalloc(self.handle, ctypes.byref(g), ctypes.byref(o), st,
+                                          _stream_ptr(self.device)), "gt_transpose_noalloc")
         return T, S, Q
 
     def run_batched(self, graphs, outs=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -48,6 +49,31 @@ gt_status graphs_args_status(const gt_csr_t *graphs, int32_t count) {
     const gt_status s = csr_args_status(graphs[i]);
     if (s != GT_OK) return s;
   }
+  return GT_OK;
+}
+
+// Scratch of gt_transpose_noalloc, for callers that cannot allocate device
+// memory: one static array per GPU, held from the module's load on that GPU
+// until the process ends.  In host code the array's name is not a device
+// address; each device's copy is resolved once, with that device current,
+// by hipGetSymbolAddress, and only that pointer is handed to kernels.
+__device__ __align__(256) unsigned char scratch[GT_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices];
+
+// The current device's copy of `scratch` (resolved on the first call there).
+gt_status current_scratch(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GT_ERR_HIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return GT_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return GT_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return GT_OK;
 }
 
@@ -533,6 +559,29 @@ gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *w
   if (workspace_bytes < plan->ws_bytes) return GT_ERR_WORKSPACE_TOO_SMALL;
   return enqueue_graph(p, *g, *out, static_cast<char *>(workspace), plan->validate, true, &plan->prof,
                        (hipStream_t)stream);
+}
+
+gt_status gt_transpose_noalloc(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, uint32_t *status_out,
+                               void *stream) {
+  if (plan == nullptr || plan->count != 1) return GT_ERR_INVALID_ARGUMENT;
+  const GraphPlan &p = plan->graphs[0];
+  gt_status s = check_io(p, g, out);
+  if (s != GT_OK) return s;
+  if (plan->ws_bytes > (size_t)GT_NOALLOC_SCRATCH_BYTES) return GT_ERR_WORKSPACE_TOO_SMALL;
+  int cur = -1, sdev = -1;
+  if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice((hipStream_t)stream, &sdev) != hipSuccess)
+    return GT_ERR_HIP;
+  if (cur != sdev) return GT_ERR_INVALID_ARGUMENT;
+  void *ws = nullptr;
+  s = current_scratch(&ws);
+  if (s != GT_OK) return s;
+  // no profiler: recording its events could create some
+  s = enqueue_graph(p, *g, *out, static_cast<char *>(ws), plan->validate, true, nullptr, (hipStream_t)stream);
+  if (s != GT_OK) return s;
+  if (status_out != nullptr &&
+      launch_copy_u32(status_out, static_cast<const uint32_t *>(ws), 1, (hipStream_t)stream) != hipSuccess)
+    return GT_ERR_HIP;
+  return GT_OK;
 }
 
 gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,

@@ -109,6 +109,7 @@ constexpr int kHugeChunks = 64;
 hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, int64_t max_huge, hipStream_t st);
 hipError_t launch_final(const FinalArgs &a, int64_t max_items, bool pay, hipStream_t st);
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t st);
 hipError_t launch_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err, hipStream_t st);
 hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile, int64_t ntiles, int32_t *out,
                            hipStream_t st);

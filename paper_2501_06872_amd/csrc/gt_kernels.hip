@@ -53,6 +53,12 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
   for (; i < n; i += s) p[i] = v;
 }
 
+__global__ void k_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t n) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t s = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += s) dst[i] = src[i];
+}
+
 // Offsets validation: O[0] = 0, nondecreasing, O[n] = m.
 __global__ void k_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -992,6 +998,14 @@ hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
   uint64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 
