@@ -128,7 +128,22 @@ enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2, GT_S
  * GT_FLAG_FEATURES makes gt_plan sample every graph and keep its feature
  * vector (gt_plan_features) whatever the policy; it then needs the sampling
  * scratch (gt_plan_scratch_size) and synchronises the stream. */
-enum { GT_FLAG_WIDE_STATUS = 1, GT_FLAG_FEATURES = 2 };
+/* Step 3 (the scatter) of GT_STRATEGY_HLH / GT_STRATEGY_ATOMIC, Section V-F:
+ * by default one workgroup per chunk of the edges, up to 2048 chunks, which
+ * the GPU's dispatcher hands to free compute units (Step 1 uses the same
+ * chunks).  GT_FLAG_STEP3_STATIC: as many chunks as workgroups of the
+ * scatter kernel fit on the device at once, each scattered by its own
+ * workgroup (the paper's static partition of Steps 1 and 3).
+ * GT_FLAG_STEP3_STEAL: the same chunks, Step 3 in the two phases the paper
+ * proposes: every workgroup first scatters the first 80% of its own chunk,
+ * then claims the remaining parts of all chunks (four of 5% each) from one
+ * atomic counter, in chunk order, until none is left.  Step 1 counts every
+ * part's HDVs separately, so a part scattered by another workgroup still
+ * places its HDV edges through LDS cursors.  GT_FLAG_STEP3_TIMES records
+ * per-chunk wall-clock stamps of Step 3 (gt_plan_step3_times).  The output
+ * does not depend on these flags beyond the order the atomics give. */
+enum { GT_FLAG_WIDE_STATUS = 1, GT_FLAG_FEATURES = 2, GT_FLAG_STEP3_STATIC = 4, GT_FLAG_STEP3_STEAL = 8,
+       GT_FLAG_STEP3_TIMES = 16 };
 
 typedef struct gt_plan_st *gt_plan_t;
 
@@ -260,6 +275,17 @@ gt_status gt_plan_packed(gt_plan_t plan, int32_t i, int32_t *packed);
 /* The strategy a plan runs for graph `i` (GT_STRATEGY_*; a probed plan
  * reports the method the probe kept). */
 gt_status gt_plan_strategy(gt_plan_t plan, int32_t i, int32_t *strategy);
+
+/* After the stream has been synchronised: the Step 3 stamps of the last
+ * transposition of graph `i` run with this plan in `workspace` (a plan of an
+ * unordered strategy built with GT_FLAG_STEP3_TIMES).  Per chunk workgroup c,
+ * out[3c], out[3c+1], out[3c+2] = wall-clock ticks at its start, when its own
+ * chunk's head (or whole chunk) was done, and at its end; at most
+ * `max_chunks` rows.  *nchunks_out = rows available; *clock_hz = ticks per
+ * second.  Blocking copy.  Errors: GT_ERR_INVALID_ARGUMENT (NULL pointers,
+ * `i` out of range, a plan without the flag), GT_ERR_HIP. */
+gt_status gt_plan_step3_times(gt_plan_t plan, int32_t i, const void *workspace, uint64_t *out,
+                              int32_t max_chunks, int32_t *nchunks_out, double *clock_hz);
 
 /* Release the plan's host memory and internal streams/events.  Work already
  * enqueued with it is unaffected. */

@@ -31,7 +31,7 @@ STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
            "gt_transpose_batched", "gt_transpose_noalloc", "gt_plan_device_status", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
-           "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
+           "gt_plan_step3_times", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
 NUM_FEATURES = 16
@@ -84,6 +84,7 @@ def lib():
         L.gt_plan_strategy.argtypes = [vp, i32, P(i32)]
         L.gt_plan_packed.argtypes = [vp, i32, P(i32)]
         L.gt_plan_destroy.argtypes = [vp]
+        L.gt_plan_step3_times.argtypes = [vp, i32, vp, vp, i32, P(i32), P(ctypes.c_double)]
         L.gt_profile.argtypes = [vp, i32]
         L.gt_profile_read.argtypes = [vp, i32, vp, vp, vp, P(i32)]
         L.gt_plan_features.argtypes = [vp, i32, vp, i32, P(i32)]
@@ -139,7 +140,7 @@ def _check_inputs(offsets, indices, payload):
             raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
 
 
-FLAG_WIDE_STATUS, FLAG_FEATURES = 1, 2
+FLAG_WIDE_STATUS, FLAG_FEATURES, FLAG_STEP3_STATIC, FLAG_STEP3_STEAL, FLAG_STEP3_TIMES = 1, 2, 4, 8, 16
 
 
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
@@ -282,6 +283,24 @@ class Plan:
             name = raw[32 * k: 32 * k + 32].split(b"\0", 1)[0].decode()
             out[name] = (ms[k], nl[k])
         return out
+
+    def step3_times(self, i=0):
+        """Per chunk workgroup of Step 3 (plans with FLAG_STEP3_TIMES):
+        uint64 wall-clock stamps [start, own head done, end]."""
+        import numpy as np
+        torch.cuda.current_stream(self.device).synchronize()
+        cnt = ctypes.c_int32()
+        hz = ctypes.c_double()
+        _check(lib().gt_plan_step3_times(self.handle, i, self.workspace.data_ptr(), None, 0, ctypes.byref(cnt),
+                                         ctypes.byref(hz)), "gt_plan_step3_times")
+        out = np.zeros((cnt.value, 3), dtype=np.uint64)
+        _check(lib().gt_plan_step3_times(self.handle, i, self.workspace.data_ptr(), out.ctypes.data, cnt.value,
+                                         ctypes.byref(cnt), ctypes.byref(hz)), "gt_plan_step3_times")
+        self._step3_hz = hz.value
+        return out
+
+    def step3_clock_hz(self):
+        return getattr(self, "_step3_hz", 100e6)
 
     def device_status(self):
         torch.cuda.current_stream(self.device).synchronize()

@@ -89,8 +89,18 @@ namespace gt {
 size_t unordered_workspace_end(GraphPlan &p, size_t base) {
   const bool hlh = p.strategy == GT_STRATEGY_HLH;
   p.kmax = hlh ? (p.hdv_max > 0 && p.hdv_max < kHlhMaxHdv ? p.hdv_max : kHlhMaxHdv) : 0;
-  p.nchunks = p.m > 0 ? std::min<int64_t>(std::max<int64_t>((p.m + 65535) / 65536, 1), 2048) : 0;
+  // chunks of at least 64K edges: up to 2048 (dispatched), or as many as
+  // workgroups of the scatter fit on the device (static, two-phase)
+  int64_t max_chunks = 2048;
+  if (p.step3 != 0) {
+    const int64_t resident = hlh_resident_workgroups();
+    max_chunks = resident > 0 ? resident : 512;
+  }
+  p.nchunks = p.m > 0 ? std::min<int64_t>(std::max<int64_t>((p.m + 65535) / 65536, 1), max_chunks) : 0;
   p.chunk = p.nchunks > 0 ? (p.m + p.nchunks - 1) / p.nchunks : 0;
+  // two-phase Step 3: a head of 80% of the chunk, then four tail parts
+  p.nparts = p.step3 == 2 ? 5 : 1;
+  p.head = p.step3 == 2 ? (p.chunk * 4) / 5 : p.chunk;
   size_t off = base;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   const size_t nv = (size_t)std::max<int64_t>(p.n, 1);
@@ -101,7 +111,9 @@ size_t unordered_workspace_end(GraphPlan &p, size_t base) {
   p.off_u_nhdv = take(4);
   p.off_u_cnt = take(4 * nv);
   p.off_u_cur = take(8 * nv);
-  p.off_u_H = take(4 * (size_t)std::max<int64_t>(p.nchunks, 1) * (size_t)std::max(p.kmax, 1));
+  p.off_u_H = take(4 * (size_t)std::max<int64_t>(p.nchunks * p.nparts, 1) * (size_t)std::max(p.kmax, 1));
+  p.off_u_steal = take(4);
+  p.off_u_times = p.step3_times ? take(24 * (size_t)std::max<int64_t>(p.nchunks, 1)) : 0;
   p.off_u_sstatus = take(8 * (size_t)((p.n + offsets_scan_tile() - 1) / offsets_scan_tile() + 1));
   p.off_u_ticket = take(4);
   return off;
@@ -161,8 +173,17 @@ void finalize_params(GraphPlan &p, size_t base) {
   p.off_dtot = take(sizeof(uint64_t) * kMaxPasses * kMaxRadix);
   p.off_bin = take(sizeof(uint64_t) * (size_t)(p.nbins_total + 1));
   p.wide_status = p.force_wide || p.m >= (int64_t(1) << 31);
-  p.off_status = take((p.wide_status ? 8 : 4) * (size_t)p.ntiles * ((size_t)1 << p.max_bits));
+  // look-back status words of the passes after the first (which places its
+  // tiles with k_hist's per-tile counts)
+  p.off_status = take(p.passes > 1 ? (p.wide_status ? 8 : 4) * (size_t)p.ntiles * ((size_t)1 << p.max_bits) : 0);
   p.off_tsrc = take(sizeof(int32_t) * (size_t)std::max<int64_t>(p.ntiles, 1));
+  {
+    const size_t r0 = (size_t)1 << p.bits[0];
+    const size_t nt = (size_t)std::max<int64_t>(p.ntiles, 1);
+    p.off_tcnt = take(sizeof(uint16_t) * nt * r0);
+    p.off_tbsum = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(tile_scan_blocks(p.ntiles), 1) * r0);
+    p.off_toff = take(sizeof(uint32_t) * nt * r0);
+  }
   const size_t m = (size_t)p.m;
   p.off_a_src = p.off_a_key = p.off_a_pay = 0;
   p.off_a2_src = p.off_a2_key = p.off_a2_pay = 0;
@@ -206,11 +227,14 @@ size_t graph_workspace_bound(int64_t n, int64_t m, bool pay) {
         finalize_params(p, 0);
         best = std::max(best, p.ws_end);
       }
-  for (int strategy : {GT_STRATEGY_HLH, GT_STRATEGY_ATOMIC}) {
-    GraphPlan p{};
-    p.n = n; p.m = m; p.pay = pay; p.strategy = strategy;
-    best = std::max(best, unordered_workspace_end(p, 0));
-  }
+  for (int strategy : {GT_STRATEGY_HLH, GT_STRATEGY_ATOMIC})
+    for (int step3 : {0, 2}) {  // the static mode needs less than the two-phase one
+      GraphPlan p{};
+      p.n = n; p.m = m; p.pay = pay; p.strategy = strategy;
+      p.step3 = step3;
+      p.step3_times = true;
+      best = std::max(best, unordered_workspace_end(p, 0));
+    }
   return best;
 }
 
@@ -263,12 +287,17 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   HistArgs h{};
   h.passes = p.passes;
   for (int i = 0; i < p.passes; ++i) { h.shift[i] = p.shift[i]; h.bits[i] = p.bits[i]; }
-  // one histogram workgroup per 4096 edges, at most kHistBlocks: a small
-  // graph neither launches nor sums partial histograms it has no edges for
-  const int hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, (p.m + 4095) / 4096));
-  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, hist_blocks, part, err, st));
-  GT_TIMED("k_digit_scan", launch_digit_scan(part, hist_blocks, h, reinterpret_cast<uint64_t *>(ws + p.off_dtot),
-                                             digit, bins, p.nbins_total, p.m, err, st));
+  // histogram workgroups take contiguous ranges of the first pass's tiles,
+  // at most kHistBlocks of them: a small graph neither launches nor sums
+  // partial histograms it has no edges for
+  const int hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles));
+  uint16_t *tcnt = reinterpret_cast<uint16_t *>(ws + p.off_tcnt);
+  uint32_t *toff = reinterpret_cast<uint32_t *>(ws + p.off_toff);
+  uint64_t *dtot = reinterpret_cast<uint64_t *>(ws + p.off_dtot);
+  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, p.tile, p.ntiles, hist_blocks, part, tcnt, err, st));
+  GT_TIMED("k_tile_scan", launch_tile_scan(tcnt, p.ntiles, 1 << p.bits[0],
+                                           reinterpret_cast<uint32_t *>(ws + p.off_tbsum), dtot, toff, st));
+  GT_TIMED("k_digit_scan", launch_digit_scan(part, hist_blocks, h, dtot, digit, bins, p.nbins_total, p.m, err, st));
   GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
 
   const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
@@ -276,10 +305,12 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
   for (int pass = 0; pass < p.passes; ++pass) {
     const bool first = pass == 0, last = pass == p.passes - 1;
-    GT_TIMED("k_fill_status", launch_fill(static_cast<uint32_t *>(status), status_words, 0u, st));
-    GT_CHK(launch_fill(ticket + pass, 1, 0u, st));
+    if (!first) {  // the first pass places its tiles with k_hist's tile offsets
+      GT_TIMED("k_fill_status", launch_fill(static_cast<uint32_t *>(status), status_words, 0u, st));
+      GT_CHK(launch_fill(ticket + pass, 1, 0u, st));
+    }
     LsdArgs a{};
-    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc;
+    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc; a.tile_off = toff;
     a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
     const bool pk = p.packed && (first != last);
     if (pk && last) a.in_key16 = reinterpret_cast<const uint16_t *>(cur_key);
@@ -359,6 +390,9 @@ static UnorderedArgs unordered_args(const GraphPlan &p, const gt_csr_t &g, const
   u.O = g.offsets; u.D = g.indices; u.P = g.payload;
   u.n = p.n; u.m = p.m;
   u.chunk = p.chunk; u.nchunks = p.nchunks; u.span = p.chunk;
+  u.nparts = p.nparts; u.head = p.head;
+  u.steal_ticket = reinterpret_cast<uint32_t *>(ws + p.off_u_steal);
+  u.times = p.step3_times ? reinterpret_cast<unsigned long long *>(ws + p.off_u_times) : nullptr;
   u.kmax = p.kmax;
   u.log2slots = kHlhLog2Slots;
   u.hdv = reinterpret_cast<const int32_t *>(ws + p.off_u_hdv);
@@ -404,6 +438,7 @@ gt_status probe_strategy(GraphPlan &p, const gt_csr_t &g, char *ws, size_t ws_by
   if (ws == nullptr || unordered_workspace_end(q, kAlign) > ws_bytes) return GT_ERR_WORKSPACE_TOO_SMALL;
   UnorderedArgs u = unordered_args(q, g, nullptr, ws);
   u.span = std::max<int64_t>(1, q.chunk / 16);
+  u.nparts = 1;  // the first sixteenth of every chunk, one row per chunk
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   gt_status status = GT_OK;
   for (auto &x : ev)
@@ -445,6 +480,7 @@ gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_
   GT_CHK(launch_fill(reinterpret_cast<uint32_t *>(u.scan_status), 2 * (uint64_t)scan_tiles, 0u, st));
   GT_CHK(launch_fill(u.scan_ticket, 1, 0u, st));
   GT_TIMED("k_scan_offsets", launch_scan_offsets(u, st));
+  GT_CHK(launch_fill(u.steal_ticket, 1, 0u, st));
   GT_TIMED("k_hlh_scatter", launch_hlh_scatter(u, st));
 #undef GT_TIMED
 #undef GT_CHK
@@ -630,6 +666,22 @@ gt_status gt_plan_packed(gt_plan_t plan, int32_t i, int32_t *packed) {
 gt_status gt_plan_strategy(gt_plan_t plan, int32_t i, int32_t *strategy) {
   if (plan == nullptr || i < 0 || i >= plan->count || strategy == nullptr) return GT_ERR_INVALID_ARGUMENT;
   *strategy = plan->graphs[i].strategy;
+  return GT_OK;
+}
+
+gt_status gt_plan_step3_times(gt_plan_t plan, int32_t i, const void *workspace, uint64_t *out,
+                              int32_t max_chunks, int32_t *nchunks_out, double *clock_hz) {
+  if (plan == nullptr || i < 0 || i >= plan->count || workspace == nullptr || nchunks_out == nullptr ||
+      clock_hz == nullptr || (max_chunks > 0 && out == nullptr))
+    return GT_ERR_INVALID_ARGUMENT;
+  const GraphPlan &p = plan->graphs[i];
+  if (p.strategy == GT_STRATEGY_STABLE || !p.step3_times) return GT_ERR_INVALID_ARGUMENT;
+  *nchunks_out = (int32_t)p.nchunks;
+  *clock_hz = hlh_clock_hz();
+  const int64_t rows = std::min<int64_t>(p.nchunks, std::max(max_chunks, 0));
+  if (rows > 0 && hipMemcpy(out, static_cast<const char *>(workspace) + p.off_u_times, 24 * (size_t)rows,
+                            hipMemcpyDeviceToHost) != hipSuccess)
+    return GT_ERR_HIP;
   return GT_OK;
 }
 

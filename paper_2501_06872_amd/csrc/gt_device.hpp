@@ -8,6 +8,12 @@ namespace gt {
 constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+// A value the compiler cannot see through: expressions computed from it are
+// recomputed rather than kept live from before this point.
+__device__ __forceinline__ int opaque_int(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
 // Stable in-wave ranking of one row of keys (< 2^bits) through LDS.
@@ -130,6 +136,26 @@ __device__ T block_excl_scan(T *s, int len, T *wsum) {
   T total = wsum[NW];
   __syncthreads();
   return total;
+}
+
+// Workgroup -> work-item order that keeps runs of consecutive items on one
+// XCD.  Workgroups are dispatched to the 8 XCDs round-robin by index, and
+// each XCD has its own L2; items that write neighbouring pieces of one output
+// region (the tiles of a partition pass, the bins of the placement kernel)
+// then complete each other's partial cache lines in the same L2 before the
+// lines are written back.  Blocks of `blk` consecutive items go to one XCD,
+// blocks round-robin over the XCDs; the item count's tail beyond whole
+// rounds keeps the identity map.  A bijection on [0, count).
+#ifndef GT_XCD_BLOCK
+#define GT_XCD_BLOCK 16
+#endif
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t i, int64_t count, int64_t blk) {
+  if (blk <= 1) return i;
+  const int64_t round = kXcds * blk;
+  if (i >= (count / round) * round) return i;
+  const int64_t x = i % kXcds, j = i / kXcds;  // XCD of workgroup i, its index there
+  return ((j / blk) * kXcds + x) * blk + j % blk;
 }
 
 // Status words of the decoupled look-back (Merrill & Garland 2016), one per

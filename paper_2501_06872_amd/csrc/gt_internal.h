@@ -34,6 +34,7 @@ struct LsdArgs {
   const int32_t *D;
   const uint32_t *P;
   const int32_t *tile_src0;
+  const uint32_t *tile_off;  // first pass: [ntiles][radix] offset of each tile within each digit
   // partitioned input (later passes)
   const int32_t *in_src;
   const uint32_t *in_key;
@@ -113,8 +114,17 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipSt
 hipError_t launch_validate_offsets(const int64_t *O, int64_t n, int64_t m, uint32_t *err, hipStream_t st);
 hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile, int64_t ntiles, int32_t *out,
                            hipStream_t st);
-hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int nblocks, uint32_t *part,
-                       uint32_t *err, hipStream_t st);
+// Step 1 in the first pass's tiles of `tile` edges (4096, 8192 or 16384):
+// per-tile 16-bit counts of the first pass's digit (tilecnt[ntiles][radix])
+// and per-workgroup partial histograms of the later passes.
+hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int64_t tile, int64_t ntiles,
+                       int nblocks, uint32_t *part, uint16_t *tilecnt, uint32_t *err, hipStream_t st);
+// Column prefix of tilecnt -> tileoff[ntiles][radix] (uint32) and the first
+// pass's digit totals (totals0[radix]); bsum holds tile_scan_blocks(ntiles)
+// * radix words.
+int64_t tile_scan_blocks(int64_t ntiles);
+hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, uint32_t *bsum, uint64_t *totals0,
+                            uint32_t *tileoff, hipStream_t st);
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
                              uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
                              uint32_t *err, hipStream_t st);

@@ -85,29 +85,41 @@ __global__ void k_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile_
   out[t] = (int32_t)lo;
 }
 
-// Step 1: digit histograms of the destinations, one LDS histogram per pass
-// and per wave (fewer same-address LDS conflicts on skewed digits).  Partial
-// histograms are written per workgroup (no global atomics) and summed by
-// k_digit_scan.
-template <int PASSES>
+// Step 1: digit histograms of the destinations, read in the tiles of the
+// first partition pass (tile t = edges [t*TILE, (t+1)*TILE)), each workgroup
+// a contiguous range of tiles.  Per tile, the counts of the first pass's
+// digit (one LDS histogram for the workgroup) are written as a row of 16-bit
+// counts, tilecnt[t][d]: their column prefix gives the first pass each
+// tile's place within every digit, so that pass needs no look-back.  The
+// digits of the
+// later passes are summed over the workgroup's range and written as partial
+// histograms (no global atomics), summed by k_digit_reduce.
+template <int PASSES, int TILE>
 __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int64_t m, int64_t n, HistArgs h,
-                                              uint32_t *__restrict__ part, uint32_t *err) {
-  constexpr int NW = 4;
-  __shared__ uint32_t s_h[NW][PASSES * kMaxRadix];
+                                              int64_t ntiles, uint32_t *__restrict__ part,
+                                              uint16_t *__restrict__ tilecnt, uint32_t *err) {
+  constexpr int NT = 256, NW = NT / kWave;
+  constexpr int LATER = PASSES > 1 ? PASSES - 1 : 1;
+  constexpr int V = TILE / 4 / NT;  // 16-byte loads per thread per tile
+  static_assert(TILE % (4 * NT) == 0, "tile of whole 16-byte rows");
+  __shared__ uint32_t s_t[kMaxRadix];              // first pass, this tile (one copy)
+  __shared__ uint32_t s_h[NW][LATER * kMaxRadix];  // later passes, the workgroup's tiles
   const int tid = threadIdx.x, w = tid / kWave;
-  for (int i = tid; i < NW * PASSES * kMaxRadix; i += blockDim.x) (&s_h[0][0])[i] = 0;
-  __syncthreads();
-  uint32_t *hw = s_h[w];
+  const int b0 = h.bits[0], r0 = 1 << b0;
+  for (int i = tid; i < NW * LATER * kMaxRadix; i += NT) (&s_h[0][0])[i] = 0;
   int sh[PASSES];
   uint32_t mk[PASSES];
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) { sh[p] = h.shift[p]; mk[p] = (1u << h.bits[p]) - 1u; }
+  auto ctr = [&](int p, uint32_t d) -> uint32_t * {
+    return p == 0 ? &s_t[d] : &s_h[w][(p - 1) * kMaxRadix + d];
+  };
   bool bad = false;
   const uint32_t un = (uint32_t)(n > 0xFFFFFFFFll ? 0xFFFFFFFFll : n);
   auto count = [&](uint32_t u) {
     bad |= u >= un;  // also catches negative indices
 #pragma unroll
-    for (int p = 0; p < PASSES; ++p) atomicAdd(&hw[p * kMaxRadix + ((u >> sh[p]) & mk[p])], 1u);
+    for (int p = 0; p < PASSES; ++p) atomicAdd(ctr(p, (u >> sh[p]) & mk[p]), 1u);
   };
   // Four consecutive destinations per lane.  Runs of equal digits (common
   // when destinations are close to their sources) are added once: per lane
@@ -123,49 +135,151 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ D, int
       const uint64_t active = __ballot(1);
       if (__all(same4 && dx == d0)) {
         if ((uint64_t)1 << (threadIdx.x & 63) == (active & -active))
-          atomicAdd(&hw[p * kMaxRadix + d0], 4u * (uint32_t)__popcll(active));
+          atomicAdd(ctr(p, d0), 4u * (uint32_t)__popcll(active));
       } else if (same4) {
-        atomicAdd(&hw[p * kMaxRadix + dx], 4u);
+        atomicAdd(ctr(p, dx), 4u);
       } else {
-        atomicAdd(&hw[p * kMaxRadix + dx], 1u);
-        atomicAdd(&hw[p * kMaxRadix + dy], 1u);
-        atomicAdd(&hw[p * kMaxRadix + dz], 1u);
-        atomicAdd(&hw[p * kMaxRadix + dw], 1u);
+        atomicAdd(ctr(p, dx), 1u);
+        atomicAdd(ctr(p, dy), 1u);
+        atomicAdd(ctr(p, dz), 1u);
+        atomicAdd(ctr(p, dw), 1u);
       }
     }
   };
-  const int64_t nvec = m >> 2;
   const uint4 *D4 = reinterpret_cast<const uint4 *>(D);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i0 = blockIdx.x * (int64_t)blockDim.x + tid;
-  for (; i0 + 3 * stride < nvec; i0 += 4 * stride) {  // four loads in flight per thread
-    const uint4 q0 = D4[i0], q1 = D4[i0 + stride], q2 = D4[i0 + 2 * stride], q3 = D4[i0 + 3 * stride];
-    count4(q0);
-    count4(q1);
-    count4(q2);
-    count4(q3);
-  }
-  for (; i0 < nvec; i0 += stride) count4(D4[i0]);
-  for (int64_t i = (nvec << 2) + blockIdx.x * (int64_t)blockDim.x + tid; i < m; i += stride) count((uint32_t)D[i]);
-  if (bad) atomicOr(err, kErrBadIndex);
-  __syncthreads();
-  uint32_t *out = part + (int64_t)blockIdx.x * kMaxPasses * kMaxRadix;
-  for (int i = tid; i < PASSES * kMaxRadix; i += blockDim.x) {
-    uint32_t c = 0;
+  const int64_t t_beg = (int64_t)blockIdx.x * ntiles / gridDim.x;
+  const int64_t t_end = ((int64_t)blockIdx.x + 1) * ntiles / gridDim.x;
+  // the loads of the next tile are issued before the current one is counted
+  uint4 q[V];
+  auto load = [&](int64_t t) {
+    const int64_t base = t * TILE;
+    if (t < t_end && base + TILE <= m) {
 #pragma unroll
-    for (int x = 0; x < NW; ++x) c += s_h[x][i];
-    out[i] = c;
+      for (int v = 0; v < V; ++v) q[v] = D4[(base >> 2) + v * NT + tid];
+    }
+  };
+  load(t_beg);
+  for (int64_t t = t_beg; t < t_end; ++t) {
+    for (int i = tid; i < r0; i += NT) s_t[i] = 0;
+    __syncthreads();
+    const int64_t base = t * TILE;
+    if (base + TILE <= m) {
+      uint4 c[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) c[v] = q[v];
+      load(t + 1);
+#pragma unroll
+      for (int v = 0; v < V; ++v) count4(c[v]);
+    } else {  // the last, ragged tile
+      for (int64_t e = base + tid; e < m; e += NT) count((uint32_t)D[e]);
+    }
+    __syncthreads();
+    uint16_t *row = tilecnt + t * r0;
+    for (int d = tid; d < r0; d += NT) {
+      row[d] = (uint16_t)s_t[d];
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(err, kErrBadIndex);
+  uint32_t *out = part + (int64_t)blockIdx.x * kMaxPasses * kMaxRadix;
+  for (int p = 1; p < PASSES; ++p)
+    for (int d = tid; d < (1 << h.bits[p]); d += NT) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int x = 0; x < NW; ++x) c += s_h[x][(p - 1) * kMaxRadix + d];
+      out[p * kMaxRadix + d] = c;
+    }
+}
+
+// Column prefix of the first pass's per-tile digit counts, over blocks of
+// kTileBlk tiles: block sums (digit-major), an exclusive scan of each digit's
+// block sums (which also yields the first pass's digit totals), then every
+// tile's offset within each digit.  Offsets are kept in 32 bits: the offset
+// of a tile that holds edges of digit d is below the digit's total, so below
+// 2^32 for every accepted edge count.
+constexpr int kTileBlk = 64;
+
+__global__ __launch_bounds__(256) void k_tile_bsum(const uint16_t *__restrict__ tilecnt, int64_t ntiles, int radix,
+                                                   int64_t nblk, uint32_t *__restrict__ bsum) {
+  const int64_t b = blockIdx.x;
+  const int64_t t0 = b * kTileBlk, t1 = t0 + kTileBlk < ntiles ? t0 + kTileBlk : ntiles;
+  for (int d = threadIdx.x; d < radix; d += blockDim.x) {
+    constexpr int U = 8;  // rows in flight
+    uint32_t s = 0;
+    int64_t t = t0;
+    for (; t + U <= t1; t += U) {
+      uint32_t c[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = tilecnt[(t + u) * radix + d];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += c[u];
+    }
+    for (; t < t1; ++t) s += tilecnt[t * radix + d];
+    bsum[(int64_t)d * nblk + b] = s;
   }
 }
 
-// Step 2 (digit level), part 1: sum the per-workgroup partial histograms.
-// Block (pass, 64-digit group); four thread groups split the partials.
+// One workgroup per digit: exclusive scan of its block sums, in place.
+__global__ __launch_bounds__(256) void k_tile_bscan(uint32_t *bsum, int64_t nblk, uint64_t *totals0) {
+  constexpr int NT = 256, ITEMS = 8;
+  __shared__ uint64_t s_w[NT / kWave + 1];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  uint32_t *row = bsum + (int64_t)blockIdx.x * nblk;
+  uint64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nblk; c0 += NT * ITEMS) {
+    const int64_t base = c0 + (int64_t)tid * ITEMS;
+    uint32_t v[ITEMS];
+    uint64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      v[k] = base + k < nblk ? row[base + k] : 0u;
+      local += v[k];
+    }
+    const uint64_t incl = wave_incl_sum64(local, lane);
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t run = 0;
+      for (int i = 0; i < NT / kWave; ++i) { const uint64_t c = s_w[i]; s_w[i] = run; run += c; }
+      s_w[NT / kWave] = run;
+    }
+    __syncthreads();
+    uint64_t run = carry + s_w[w] + incl - local;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (base + k < nblk) {
+        row[base + k] = (uint32_t)run;
+        run += v[k];
+      }
+    carry += s_w[NT / kWave];
+    __syncthreads();
+  }
+  if (tid == 0) totals0[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_tile_off(const uint16_t *__restrict__ tilecnt, int64_t ntiles, int radix,
+                                                  int64_t nblk, const uint32_t *__restrict__ bpre,
+                                                  uint32_t *__restrict__ tileoff) {
+  const int64_t b = blockIdx.x;
+  const int64_t t0 = b * kTileBlk, t1 = t0 + kTileBlk < ntiles ? t0 + kTileBlk : ntiles;
+  for (int d = threadIdx.x; d < radix; d += blockDim.x) {
+    uint32_t run = bpre[(int64_t)d * nblk + b];
+    for (int64_t t = t0; t < t1; ++t) {
+      tileoff[t * radix + d] = run;
+      run += tilecnt[t * radix + d];
+    }
+  }
+}
+
+// Step 2 (digit level), part 1: sum the per-workgroup partial histograms of
+// the later passes.  Block (pass, 64-digit group); four thread groups split
+// the partials.
 __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict__ part, int nblocks, HistArgs h,
                                                       uint64_t *totals) {
   __shared__ uint64_t s_sum[4][64];
   const int p = blockIdx.x / (kMaxRadix / 64), g = blockIdx.x % (kMaxRadix / 64);
   const int tid = threadIdx.x, d = g * 64 + (tid & 63), q = tid >> 6;
-  if (p >= h.passes) return;
+  if (p == 0 || p >= h.passes) return;  // the first pass's totals come from k_tile_bscan
   const int radix = 1 << h.bits[p];
   uint64_t s = 0;
   if (d < radix) {
@@ -234,20 +348,25 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
   __shared__ uint16_t s_bnd[PK_IN ? kMaxRadix : 1];
   __shared__ int32_t s_fl[3];
 
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int tid = threadIdx.x;
+  int lane = tid & (kWave - 1), w = tid / kWave;
   const int radix = 1 << a.bits;
   const uint32_t dmask = (uint32_t)radix - 1u;
 
   lds_zero16(&s_wcnt[0][0], WAVES * RADIX * 2, tid, NT);
   lds_zero16(s_stage, 2 * WAVES * RADIX * 4, tid, NT);
-  if (tid == 0) s_tile = (int64_t)atomicAdd(a.ticket, 1u);
+  // first pass: runs of consecutive tiles per XCD (their digit runs meet in
+  // one L2); later passes: tiles in ticket order, for the look-back
+  if (tid == 0)
+    s_tile = CSR_IN ? xcd_item(blockIdx.x, (a.m + TILE - 1) / TILE, GT_XCD_BLOCK) : (int64_t)atomicAdd(a.ticket, 1u);
   if (PK_IN && tid < 3) s_fl[tid] = 0;
   __syncthreads();
   // The first pass takes its tiles from the end of the edge array: the
   // sources of a natural-order graph thin out towards high IDs, and a tile
   // there fills its sources from up to ~10^5 offsets, so those tiles start
-  // first instead of closing the launch.  Its look-back then runs over the
-  // tiles behind it (suffix counts), in the order the tiles are taken.
+  // first instead of closing the launch.  It places its tiles with the
+  // per-tile digit offsets of k_hist (no look-back); later passes take their
+  // tiles from a ticket and run a decoupled look-back over them.
   const int64_t ntiles = (a.m + TILE - 1) / TILE;
   const int64_t order = s_tile;  // position in the look-back chain
   const int64_t tile = CSR_IN ? ntiles - 1 - order : order;
@@ -296,13 +415,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     if constexpr (kEarly) load_src_pay();
   }
   // first pass: the source of the tile's first edge and the first offset
-  // each thread inspects for the source marks, also loaded up front
+  // each thread inspects for the source marks (loaded after the staging)
   int64_t u0 = 0, o_first = 0;
-  if constexpr (CSR_IN) {
-    u0 = a.tile_src0[tile];
-    const int64_t u = u0 + 1 + tid;
-    o_first = u < a.n ? a.O[u] : a.m;
-  }
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
   // Local positions stay below the tile size: two per register.
@@ -327,12 +441,19 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     }
     s_tot[d] = run;
     s_toff[d] = run;
-    lookback_publish<SW>(static_cast<SW *>(a.status), order, radix, d, run);
+    if constexpr (!CSR_IN) lookback_publish<SW>(static_cast<SW *>(a.status), order, radix, d, run);
   }
   // the scan below reads s_toff in blocks of radix / NT entries per thread,
   // so with more digits than threads it reads other threads' writes
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets (ends with a barrier)
+  // first pass (no look-back wait below to bound the scheduler): the row
+  // addresses of the ranking are recomputed from here on rather than kept
+  // in registers across the scan, which keeps six waves per SIMD
+  if constexpr (CSR_IN) {
+    lane = opaque_int(lane);
+    w = opaque_int(w);
+  }
 
   // stage keys in sorted order (the keys leave registers before the wait);
   // PK_IN: with the edge's position in the tile in the upper half (its
@@ -367,13 +488,21 @@ __global__ __launch_bounds__(WAVES *kWave) void k_lsd(LsdArgs a) {
     }
   }
   if constexpr (!kEarly) load_src_pay();
-  // look-back per digit across tiles; staged slot i of digit d goes to
-  // s_gbase[d] + i
+  if constexpr (CSR_IN) {  // loaded here, where fewer values are live
+    u0 = a.tile_src0[tile];
+    const int64_t u = u0 + 1 + tid;
+    o_first = u < a.n ? a.O[u] : a.m;
+  }
+  // the tile's place within each digit (first pass: the column prefix of
+  // k_hist's tile counts; later passes: look-back across tiles); staged
+  // slot i of digit d goes to s_gbase[d] + i
   for (int d = tid; d < radix; d += NT) {
-    const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), order, radix, d, s_tot[d]);
-    // ascending tiles: digit start + the earlier tiles' count; descending
-    // (first pass): digit end - the later tiles' count - this tile's count
-    s_gbase[d] = CSR_IN ? a.digit_start[d + 1] - excl - s_tot[d] - s_toff[d] : a.digit_start[d] + excl - s_toff[d];
+    if constexpr (CSR_IN) {
+      s_gbase[d] = a.digit_start[d] + a.tile_off[tile * radix + d] - s_toff[d];
+    } else {
+      const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), order, radix, d, s_tot[d]);
+      s_gbase[d] = a.digit_start[d] + excl - s_toff[d];
+    }
   }
   __syncthreads();
 
@@ -742,7 +871,8 @@ __global__ __launch_bounds__(WAVES *kWave) void k_final(FinalArgs a) {
   __shared__ uint64_t s_cur[FW];
   __shared__ uint32_t s_w32[NT / kWave + 1];
 
-  const int64_t item = blockIdx.x;
+  // runs of consecutive items (neighbouring CSC windows) per XCD
+  const int64_t item = xcd_item(blockIdx.x, gridDim.x, GT_XCD_BLOCK);
   const uint32_t total = *a.total_items;
   const uint4 dsc = a.item_desc[item];  // grid = the most items a plan can have
   if (item >= (int64_t)total) return;
@@ -1025,13 +1155,40 @@ hipError_t launch_tile_src(const int64_t *O, int64_t n, int64_t m, int64_t tile,
   return hipGetLastError();
 }
 
-hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int nblocks, uint32_t *part,
-                       uint32_t *err, hipStream_t st) {
+template <int TILE>
+static void launch_hist_t(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int64_t ntiles, int nblocks,
+                          uint32_t *part, uint16_t *tilecnt, uint32_t *err, hipStream_t st) {
   switch (h.passes) {
-    case 1: hipLaunchKernelGGL(k_hist<1>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
-    case 2: hipLaunchKernelGGL(k_hist<2>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
-    default: hipLaunchKernelGGL(k_hist<3>, dim3(nblocks), dim3(256), 0, st, D, m, n, h, part, err); break;
+    case 1: hipLaunchKernelGGL((k_hist<1, TILE>), dim3(nblocks), dim3(256), 0, st, D, m, n, h, ntiles, part, tilecnt,
+                               err); break;
+    case 2: hipLaunchKernelGGL((k_hist<2, TILE>), dim3(nblocks), dim3(256), 0, st, D, m, n, h, ntiles, part, tilecnt,
+                               err); break;
+    default: hipLaunchKernelGGL((k_hist<3, TILE>), dim3(nblocks), dim3(256), 0, st, D, m, n, h, ntiles, part,
+                                tilecnt, err); break;
   }
+}
+
+hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h, int64_t tile, int64_t ntiles,
+                       int nblocks, uint32_t *part, uint16_t *tilecnt, uint32_t *err, hipStream_t st) {
+  if (ntiles <= 0 || nblocks <= 0) return hipSuccess;
+  switch (tile) {
+    case 4096: launch_hist_t<4096>(D, m, n, h, ntiles, nblocks, part, tilecnt, err, st); break;
+    case 8192: launch_hist_t<8192>(D, m, n, h, ntiles, nblocks, part, tilecnt, err, st); break;
+    case 16384: launch_hist_t<16384>(D, m, n, h, ntiles, nblocks, part, tilecnt, err, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int64_t tile_scan_blocks(int64_t ntiles) { return (ntiles + kTileBlk - 1) / kTileBlk; }
+
+hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, uint32_t *bsum, uint64_t *totals0,
+                            uint32_t *tileoff, hipStream_t st) {
+  const int64_t nblk = tile_scan_blocks(ntiles);
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_bsum, dim3((unsigned)nblk), dim3(256), 0, st, tilecnt, ntiles, radix, nblk, bsum);
+  hipLaunchKernelGGL(k_tile_bscan, dim3((unsigned)radix), dim3(256), 0, st, bsum, nblk, totals0);
+  hipLaunchKernelGGL(k_tile_off, dim3((unsigned)nblk), dim3(256), 0, st, tilecnt, ntiles, radix, nblk, bsum, tileoff);
   return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct GraphPlan {
   bool force_wide;
   // workspace byte offsets (relative to the workspace start)
   size_t off_err, off_ticket, off_part, off_digit, off_dtot, off_bin, off_status, off_tsrc;
+  size_t off_tcnt, off_tbsum, off_toff;  // first pass: per-tile digit counts, block sums, tile offsets
   size_t off_a_src, off_a_key, off_a_pay, off_a2_src, off_a2_key, off_a2_pay;
   size_t off_b_src, off_b_key, off_b_pay;
   size_t off_nch, off_ibase, off_ibin, off_itotal, off_sstatus, off_cntab, off_big, off_huge;
@@ -40,6 +41,15 @@ struct GraphPlan {
   int32_t hdv_max, kmax;
   uint64_t seed;
   int64_t nchunks, chunk;
+  // Step 3 of the unordered strategies: 0 = one chunk per workgroup, up to
+  // 2048 chunks (the dispatcher balances them); 1 = static, as many chunks
+  // as resident workgroups; 2 = the two-phase scheme of Section V-F (static
+  // heads, tail parts claimed atomically); times: record per-chunk stamps
+  int step3 = 0;
+  bool step3_times = false;
+  int nparts = 1;
+  int64_t head = 0;
+  size_t off_u_steal = 0, off_u_times = 0;
   size_t off_u_samp, off_u_hist, off_u_thr, off_u_hdv, off_u_nhdv, off_u_cnt, off_u_cur, off_u_H, off_u_sstatus,
       off_u_ticket;
   size_t ws_end;

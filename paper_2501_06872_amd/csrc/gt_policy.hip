@@ -145,6 +145,8 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
     p.m = graphs[i].m;
     p.pay = graphs[i].payload != nullptr;
     p.force_wide = (opt.flags & GT_FLAG_WIDE_STATUS) != 0;
+    p.step3 = (opt.flags & GT_FLAG_STEP3_STEAL) ? 2 : ((opt.flags & GT_FLAG_STEP3_STATIC) ? 1 : 0);
+    p.step3_times = (opt.flags & GT_FLAG_STEP3_TIMES) != 0;
     p.config = -1;
     p.strategy = opt.strategy;
     p.hdv_max = opt.hdv_max;

@@ -18,12 +18,21 @@ struct UnorderedArgs {
   int64_t chunk;      // edges per chunk (one workgroup each, same map in Steps 1 and 3)
   int64_t nchunks;
   int64_t span;       // edges Step 1 counts from the start of each chunk (chunk, or less in the probe)
+  // Parts of a chunk (Section V-F, Step 3 in two phases): nparts == 1, the
+  // whole chunk; else a head of `head` edges, which the chunk's own
+  // workgroup scatters first, and nparts - 1 equal tail parts that any
+  // workgroup claims from `steal_ticket` once its head is done.  Step 1
+  // counts every part's HDVs separately, so each part has its own HDV ranges.
+  int nparts;
+  int64_t head;
+  uint32_t *steal_ticket;
+  unsigned long long *times;  // NULL, or [nchunks][3] wall-clock stamps of Step 3: start, head done, end
   const int32_t *hdv;     // [kmax] HDV list
   const uint32_t *nhdv;   // device scalar (NULL: no HDVs, Atomic GT)
   int32_t kmax;
   int log2slots;
   uint32_t *cnt;          // [n] in-degrees
-  uint32_t *H;            // [nchunks][kmax] per-chunk HDV counts -> column prefixes
+  uint32_t *H;            // [nchunks * nparts][kmax] per-part HDV counts -> column prefixes
   int64_t *T;
   int32_t *S;
   uint32_t *Q;
@@ -40,5 +49,10 @@ hipError_t launch_hdv_colscan(const UnorderedArgs &a, hipStream_t st);
 int64_t offsets_scan_tile();
 hipError_t launch_scan_offsets(const UnorderedArgs &a, hipStream_t st);
 hipError_t launch_hlh_scatter(const UnorderedArgs &a, hipStream_t st);
+// Workgroups of k_hlh_scatter resident on the whole device at once (0 when
+// the query fails): the chunk count of the static and two-phase Step 3.
+int64_t hlh_resident_workgroups();
+// Wall-clock ticks per second of the Step 3 time stamps.
+double hlh_clock_hz();
 
 }  // namespace gt

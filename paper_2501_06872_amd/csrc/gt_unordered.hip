@@ -96,6 +96,28 @@ __device__ __forceinline__ Run lane_runs(uint32_t v, bool ok, int lane) {
   return r;
 }
 
+// Edge range [lo, hi) of part `part` of chunk c.  One part: the chunk (Step 1
+// of the probe counts only its first `span` edges).  Several: the head, then
+// the tail cut into nparts - 1 near-equal parts.
+__device__ __forceinline__ void part_range(const UnorderedArgs &a, int64_t c, int part, int64_t &lo, int64_t &hi) {
+  const int64_t beg = c * a.chunk;
+  const int64_t end = beg + a.chunk < a.m ? beg + a.chunk : a.m;
+  if (a.nparts <= 1) {
+    lo = beg;
+    hi = beg + a.span < end ? beg + a.span : end;
+    return;
+  }
+  const int64_t hend = beg + a.head < end ? beg + a.head : end;
+  if (part == 0) {
+    lo = beg;
+    hi = hend;
+    return;
+  }
+  const int64_t tl = end - hend, nt = a.nparts - 1;
+  lo = hend + tl * (part - 1) / nt;
+  hi = hend + tl * part / nt;
+}
+
 }  // namespace
 
 // Step 0 (selection): histogram of sampled frequencies >= 2 (capped).
@@ -130,7 +152,8 @@ __global__ __launch_bounds__(256) void k_hdv_compact(const int32_t *keys, const 
   if (c >= 2 && cc >= t) hdv[atomicAdd(nhdv, 1u)] = keys[i];
 }
 
-// Step 1: in-degrees.  Workgroup c owns edges [c*chunk, (c+1)*chunk).
+// Step 1: in-degrees.  Workgroup c owns edges [c*chunk, (c+1)*chunk); the
+// HDV counts of every part of the chunk go to a row of their own.
 __global__ __launch_bounds__(kUNT) void k_hlh_count(UnorderedArgs a) {
   __shared__ int32_t s_key[1 << kHlhLog2Slots];
   __shared__ uint16_t s_idx[1 << kHlhLog2Slots];
@@ -140,41 +163,56 @@ __global__ __launch_bounds__(kUNT) void k_hlh_count(UnorderedArgs a) {
   const uint32_t nh = a.nhdv ? *a.nhdv : 0u;
   for (uint32_t h = tid; h < nh; h += kUNT) s_cnt[h] = 0u;
   tab.build(a.hdv, nh, tid, kUNT);
-  const int64_t beg = (int64_t)blockIdx.x * a.chunk;
-  const int64_t end = beg + a.span < a.m ? beg + a.span : a.m;
   const uint32_t un = (uint32_t)a.n;
   bool bad = false;
-  for (int64_t base = beg; base < end; base += kUNT) {
-    const int64_t e = base + tid;
-    const bool in = e < end;
-    const uint32_t v = in ? (uint32_t)a.D[e] : 0xFFFFFFFFu;
-    const bool ok = in && v < un;
-    bad |= in && !ok;
-    const Run r = lane_runs(v, ok, lane);
-    if (r.head) {
-      const int h = tab.find(v);
-      if (h >= 0) atomicAdd(&s_cnt[h], r.len);
-      else atomicAdd(&a.cnt[v], r.len);
+  for (int part = 0; part < a.nparts; ++part) {
+    int64_t beg, end;
+    part_range(a, blockIdx.x, part, beg, end);
+    for (int64_t base = beg; base < end; base += kUNT) {
+      const int64_t e = base + tid;
+      const bool in = e < end;
+      const uint32_t v = in ? (uint32_t)a.D[e] : 0xFFFFFFFFu;
+      const bool ok = in && v < un;
+      bad |= in && !ok;
+      const Run r = lane_runs(v, ok, lane);
+      if (r.head) {
+        const int h = tab.find(v);
+        if (h >= 0) atomicAdd(&s_cnt[h], r.len);
+        else atomicAdd(&a.cnt[v], r.len);
+      }
     }
+    __syncthreads();
+    uint32_t *row = a.H + ((int64_t)blockIdx.x * a.nparts + part) * a.kmax;
+    for (uint32_t h = tid; h < nh; h += kUNT) {
+      row[h] = s_cnt[h];
+      s_cnt[h] = 0u;
+    }
+    __syncthreads();
   }
   if (bad) atomicOr(a.err, kErrBadIndex);
-  __syncthreads();
-  uint32_t *row = a.H + (int64_t)blockIdx.x * a.kmax;
-  for (uint32_t h = tid; h < nh; h += kUNT) row[h] = s_cnt[h];
 }
 
-// Step 2, HDV part: per HDV, exclusive prefix of its per-chunk counts over
-// the chunks (in place) and its total in-degree.
+// Step 2, HDV part: per HDV, exclusive prefix of its per-part counts over
+// the parts of all chunks, in order (in place), and its total in-degree.
 __global__ __launch_bounds__(256) void k_hdv_colscan(UnorderedArgs a) {
   const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nh = a.nhdv ? *a.nhdv : 0u;
   if (h >= nh) return;
+  // B rows in flight per thread: the rows are independent loads, only the
+  // running sum is sequential
+  constexpr int B = 16;
+  const int64_t rows = a.nchunks * a.nparts;
   uint32_t run = 0;
-  for (int64_t c = 0; c < a.nchunks; ++c) {
-    uint32_t *p = a.H + c * a.kmax + h;
-    const uint32_t t = *p;
-    *p = run;
-    run += t;
+  for (int64_t c0 = 0; c0 < rows; c0 += B) {
+    uint32_t t[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) t[k] = c0 + k < rows ? a.H[(c0 + k) * a.kmax + h] : 0u;
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (c0 + k < rows) {
+        a.H[(c0 + k) * a.kmax + h] = run;
+        run += t[k];
+      }
   }
   a.cnt[a.hdv[h]] = run;
 }
@@ -220,71 +258,69 @@ __global__ __launch_bounds__(NT) void k_scan_offsets(UnorderedArgs a) {
   if (tile == 0 && tid == 0) a.T[a.n] = a.m;
 }
 
-// Step 3: scatter.  Same chunks as Step 1; each chunk is processed in tiles
-// of kUTile edges whose sources are derived from the offsets in LDS.
-__global__ __launch_bounds__(kUNT) void k_hlh_scatter(UnorderedArgs a) {
+// Step 3, one part [beg, end) whose HDV ranges start at row `row` of H:
+// tiles of kUTile edges whose sources are derived from the offsets in LDS.
+struct ScatterLds {
+  unsigned long long *cur;  // [kHlhMaxHdv] HDV cursors
+  uint32_t *src;            // [kUTile]
+  uint32_t *wmax;           // [kUNT / kWave]
+  int64_t *u0;
+};
+
+__device__ void scatter_part(const UnorderedArgs &a, const HdvTable &tab, uint32_t nh, int64_t row, int64_t beg,
+                             int64_t end, const ScatterLds &l) {
   constexpr int ITEMS = kUTile / kUNT;
-  __shared__ int32_t s_key[1 << kHlhLog2Slots];
-  __shared__ uint16_t s_idx[1 << kHlhLog2Slots];
-  __shared__ unsigned long long s_cur[kHlhMaxHdv];
-  __shared__ uint32_t s_src[kUTile];
-  __shared__ uint32_t s_wmax[kUNT / kWave];
-  __shared__ int64_t s_u0;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  HdvTable tab{s_key, s_idx, a.log2slots, 0};
-  const uint32_t nh = a.nhdv ? *a.nhdv : 0u;
-  const int64_t beg = (int64_t)blockIdx.x * a.chunk;
-  const int64_t end = beg + a.chunk < a.m ? beg + a.chunk : a.m;
   for (uint32_t h = tid; h < nh; h += kUNT)
-    s_cur[h] = (unsigned long long)a.T[a.hdv[h]] + a.H[(int64_t)blockIdx.x * a.kmax + h];
-  if (tid == 0) {  // source of the chunk's first edge: the largest u with O[u] <= beg
+    l.cur[h] = (unsigned long long)a.T[a.hdv[h]] + a.H[row * a.kmax + h];
+  if (tid == 0) {  // source of the part's first edge: the largest u with O[u] <= beg
     int64_t lo = 0, hi = a.n;
     while (hi - lo > 1) {
       const int64_t mid = (lo + hi) >> 1;
       if (a.O[mid] <= beg) lo = mid; else hi = mid;
     }
-    s_u0 = lo;
+    *l.u0 = lo;
   }
-  tab.build(a.hdv, nh, tid, kUNT);  // ends with a barrier
+  __syncthreads();
   const uint32_t un = (uint32_t)a.n;
   for (int64_t tb = beg; tb < end; tb += kUTile) {
     const int cnt = (int)(end - tb < kUTile ? end - tb : kUTile);
     // sources: mark the first edge of every vertex starting in the tile,
     // then fill forward with a running maximum
-    const int64_t u0 = s_u0;  // source of the tile's first edge unless a vertex starts exactly there
-    for (int i = tid; i < kUTile; i += kUNT) s_src[i] = i == 0 ? (uint32_t)u0 : 0u;
+    const int64_t u0 = *l.u0;  // source of the tile's first edge unless a vertex starts exactly there
+    for (int i = tid; i < kUTile; i += kUNT) l.src[i] = i == 0 ? (uint32_t)u0 : 0u;
     __syncthreads();
     for (int64_t u = u0 + 1 + tid; u < a.n; u += kUNT) {
       const int64_t o = a.O[u];
       if (o >= tb + cnt) break;
-      if (o >= tb) atomicMax(&s_src[o - tb], (uint32_t)u);
+      if (o >= tb) atomicMax(&l.src[o - tb], (uint32_t)u);
     }
     __syncthreads();
     uint32_t carry = 0;
     for (int r = 0; r < ITEMS; ++r) {  // wave w owns rows [w*ITEMS, (w+1)*ITEMS)
       const int i = (w * ITEMS + r) * kWave + lane;
-      uint32_t x = wave_incl_max(s_src[i], lane);
+      uint32_t x = wave_incl_max(l.src[i], lane);
       x = x > carry ? x : carry;
-      s_src[i] = x;
+      l.src[i] = x;
       carry = wave_last(x);
     }
-    if (lane == 0) s_wmax[w] = carry;
+    if (lane == 0) l.wmax[w] = carry;
     __syncthreads();
     uint32_t before = 0;
-    for (int i = 0; i < w; ++i) before = before > s_wmax[i] ? before : s_wmax[i];
+    for (int i = 0; i < w; ++i) before = before > l.wmax[i] ? before : l.wmax[i];
     for (int r = 0; r < ITEMS; ++r) {
       const int i = (w * ITEMS + r) * kWave + lane;
       const bool in = i < cnt;
       const uint32_t v = in ? (uint32_t)a.D[tb + i] : 0xFFFFFFFFu;
       const bool ok = in && v < un;
-      uint32_t src = s_src[i];
+      uint32_t src = l.src[i];
       src = src > before ? src : before;
       const uint32_t pay = (in && a.P) ? a.P[tb + i] : 0u;
       const Run run = lane_runs(v, ok, lane);
       unsigned long long pos0 = 0;
       if (run.head) {
         const int h = tab.find(v);
-        pos0 = h >= 0 ? atomicAdd(&s_cur[h], (unsigned long long)run.len)
+        pos0 = h >= 0 ? atomicAdd(&l.cur[h], (unsigned long long)run.len)
                       : atomicAdd(&a.cur[v], (unsigned long long)run.len);
       }
       const unsigned long long pos = __shfl(pos0, run.head_lane) + (unsigned long long)(lane - run.head_lane);
@@ -296,10 +332,56 @@ __global__ __launch_bounds__(kUNT) void k_hlh_scatter(UnorderedArgs a) {
     __syncthreads();
     if (tid == kUNT - 1) {  // carry the source of the tile's last edge
       uint32_t last = 0;
-      for (int i = 0; i < kUNT / kWave; ++i) last = last > s_wmax[i] ? last : s_wmax[i];
-      s_u0 = last;
+      for (int i = 0; i < kUNT / kWave; ++i) last = last > l.wmax[i] ? last : l.wmax[i];
+      *l.u0 = last;
     }
     __syncthreads();
+  }
+}
+
+// Step 3: scatter, with the chunk -> workgroup map of Step 1.  Phase 1:
+// workgroup c scatters the head of chunk c (the whole chunk when a chunk has
+// one part).  Phase 2 (Section V-F's proposal for the load imbalance of
+// Step 3): every workgroup whose head is done claims tail parts, in chunk
+// order, from one atomic ticket until none is left.
+__global__ __launch_bounds__(kUNT) void k_hlh_scatter(UnorderedArgs a) {
+  __shared__ int32_t s_key[1 << kHlhLog2Slots];
+  __shared__ uint16_t s_idx[1 << kHlhLog2Slots];
+  __shared__ unsigned long long s_cur[kHlhMaxHdv];
+  __shared__ uint32_t s_src[kUTile];
+  __shared__ uint32_t s_wmax[kUNT / kWave];
+  __shared__ int64_t s_u0;
+  __shared__ int64_t s_claim;
+  const int tid = threadIdx.x;
+  const unsigned long long t_start = a.times ? wall_clock64() : 0ull;
+  HdvTable tab{s_key, s_idx, a.log2slots, 0};
+  const uint32_t nh = a.nhdv ? *a.nhdv : 0u;
+  tab.build(a.hdv, nh, tid, kUNT);  // ends with a barrier
+  const ScatterLds l{s_cur, s_src, s_wmax, &s_u0};
+  const int64_t c = blockIdx.x;
+  int64_t lo, hi;
+  part_range(a, c, 0, lo, hi);
+  if (a.nparts <= 1) hi = c * a.chunk + a.chunk < a.m ? c * a.chunk + a.chunk : a.m;  // the whole chunk
+  scatter_part(a, tab, nh, c * a.nparts, lo, hi, l);
+  const unsigned long long t_head = a.times ? wall_clock64() : 0ull;
+  if (a.nparts > 1) {
+    const int64_t ntail = a.nchunks * (a.nparts - 1);
+    while (true) {
+      if (tid == 0) s_claim = (int64_t)atomicAdd(a.steal_ticket, 1u);
+      __syncthreads();
+      const int64_t t = s_claim;
+      __syncthreads();  // every thread has the claim before the next one overwrites it
+      if (t >= ntail) break;
+      const int64_t cc = t / (a.nparts - 1);
+      const int part = 1 + (int)(t % (a.nparts - 1));
+      part_range(a, cc, part, lo, hi);
+      scatter_part(a, tab, nh, cc * a.nparts + part, lo, hi, l);
+    }
+  }
+  if (a.times && tid == 0) {
+    a.times[3 * c] = t_start;
+    a.times[3 * c + 1] = t_head;
+    a.times[3 * c + 2] = wall_clock64();
   }
 }
 
@@ -340,6 +422,26 @@ hipError_t launch_hlh_scatter(const UnorderedArgs &a, hipStream_t st) {
   if (a.m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hlh_scatter, dim3((unsigned)a.nchunks), dim3(kUNT), 0, st, a);
   return hipGetLastError();
+}
+
+int64_t hlh_resident_workgroups() {
+  static int64_t cached = -1;
+  if (cached >= 0) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hlh_scatter, kUNT, 0) != hipSuccess)
+    return 0;
+  cached = (int64_t)cus * per_cu;
+  return cached;
+}
+
+double hlh_clock_hz() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
+      hipSuccess || khz <= 0)
+    return 100e6;  // the 100 MHz constant clock of this GPU family
+  return 1e3 * khz;
 }
 
 }  // namespace gt

@@ -382,3 +382,55 @@ def test_counter_check_quiet_on_valid_graphs(hip_device):
     say("[case] counter checks on rmat18 (natural order: many big bins)")
     T, S, Q, st, params = gpu_transpose(O, D, P, hip_device)
     assert st == gt.GT_OK
+
+
+@pytest.mark.parametrize("permute,payload", [(False, False), (True, True)])
+def test_csc_input_transposes_back_to_the_csr(hip_device, permute, payload):
+    """The CSC representations of Section V-A: the GPU's own CSC of an R-MAT
+    scale-18 graph (natural order, and randomly relabelled with a payload),
+    given back to the library as input (CSC -> CSR), returns the generated
+    CSR exactly (its lists ascend, multi-edges in generation order), and both
+    directions equal the oracle's."""
+    import paper_2501_06872_amd as gt
+    O, D, P = gen.rmat(18, 16, seed=18, permute=permute, payload=payload)
+    label = f"rmat18{'p' if permute else ''} CSC input"
+    say(f"[case] {label}: n={O.size - 1} m={D.size} payload={payload}")
+    T, S, Q, st, _ = gpu_transpose(O, D, P, hip_device)
+    assert st == gt.GT_OK
+    rT, rS, rQ = oracle.transpose(O, D, P)
+    assert np.array_equal(T, rT) and np.array_equal(S, rS)
+    if payload:
+        assert np.array_equal(Q, rQ)
+    # the CSC as input: offsets T, "destinations" S, payload Q
+    T2, S2, Q2, st2, _ = gpu_transpose(T, S, Q, hip_device)
+    assert st2 == gt.GT_OK
+    assert np.array_equal(T2, O), f"{label}: offsets do not return"
+    assert np.array_equal(S2, D), f"{label}: lists do not return"
+    if payload:
+        assert np.array_equal(Q2, P), f"{label}: payload does not return"
+    oT, oS, oQ = oracle.transpose(T, S, Q)
+    assert np.array_equal(T2, oT) and np.array_equal(S2, oS)
+    if payload:
+        assert np.array_equal(Q2, oQ)
+
+
+@pytest.mark.parametrize("variant", [1, 3, 4])
+def test_first_pass_tile_counts(hip_device, variant):
+    """The first partition pass places each tile with the column prefix of
+    k_hist's per-tile digit counts (16-bit per tile and digit): a tile whose
+    edges all share one digit (the largest count a tile can hold), edge
+    counts around whole tiles and a ragged last tile, one and two passes."""
+    tile = {1: 8192, 3: 4096, 4: 16384}[variant]
+    rng = np.random.default_rng(variant)
+    for m in (1, 3, tile - 1, tile, tile + 1, 3 * tile + 5):
+        n = 5000
+        O = np.sort(rng.integers(0, m + 1, size=n + 1)).astype(np.int64)
+        O[0], O[-1] = 0, m
+        D = np.full(m, 4999, dtype=np.int32)  # every edge into one vertex: one digit per pass
+        if m != tile:  # a whole tile of one digit stays: its count is the tile size
+            D[::7] = rng.integers(0, n, size=D[::7].size)
+        for u in range(n):
+            D[O[u]:O[u + 1]].sort()
+        for fb, db in ((9, 9), (4, 5)):
+            assert_parity(O, D, None, hip_device, f"tile counts variant {variant} m={m} fine={fb} digit={db}",
+                          policy=1, fine_bits=fb, digit_bits=db, variant=variant)

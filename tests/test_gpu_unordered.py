@@ -128,3 +128,46 @@ def test_probe_picks_a_method_and_stays_exact(hip_device):
         assert np.array_equal(cS, oS)
         if P is not None:
             assert np.array_equal(cQ, oQ)
+
+
+@pytest.mark.parametrize("mode", ["static", "steal"])
+@pytest.mark.parametrize("strategy", ["hlh", "atomic"])
+def test_step3_static_and_two_phase(hip_device, strategy, mode):
+    """Step 3 with one chunk per resident workgroup (static), and in the two
+    phases of Section V-F (each workgroup scatters the head of its chunk,
+    then claims tail parts atomically): offsets exact and every list equal to
+    the oracle's as a multiset, on skewed, hub, tiny and ragged inputs, with
+    the per-chunk time stamps recorded."""
+    import paper_2501_06872_amd as gt
+    flags = (gt.FLAG_STEP3_STEAL if mode == "steal" else gt.FLAG_STEP3_STATIC) | gt.FLAG_STEP3_TIMES
+    O, D, P = gen.rmat(19, 16, seed=12, permute=False, payload=True)
+    assert_unordered_parity(O, D, P, hip_device, f"rmat19 {mode}", strategy, flags=flags)
+    n = 60000  # a hub: every vertex points at vertex 5 four times
+    O = np.arange(0, 4 * n + 1, 4, dtype=np.int64)
+    D = np.full(4 * n, 5, dtype=np.int32)
+    assert_unordered_parity(O, D, np.arange(4 * n, dtype=np.uint32), hip_device, f"star {mode}", strategy,
+                            flags=flags)
+    # fewer edges than chunks, and a ragged count
+    rng = np.random.default_rng(8)
+    O, D, P = random_csr(rng, 700, 3, payload=True)
+    assert_unordered_parity(O, D, P, hip_device, f"tiny {mode}", strategy, flags=flags)
+    O, D, _ = gen.uniform((1 << 17) + 333, 7, seed=2)
+    assert_unordered_parity(O, D, None, hip_device, f"uniform ragged {mode}", strategy, flags=flags)
+
+
+def test_step3_time_stamps(hip_device):
+    import paper_2501_06872_amd as gt
+    from paper_2501_06872_amd import step3
+    O, D, P = gen.rmat(18, 16, seed=4, permute=True)
+    g = to_dev(O, D, P, hip_device)
+    for mode, flag in (("static", gt.FLAG_STEP3_STATIC), ("steal", gt.FLAG_STEP3_STEAL)):
+        say(f"[case] step-3 time stamps, {mode}")
+        plan = gt.Plan([g], gt.make_options(strategy=gt.STRATEGY_HLH, flags=flag | gt.FLAG_STEP3_TIMES))
+        plan.run(*g)
+        torch.cuda.synchronize()
+        st = plan.step3_times()
+        assert st.shape[1] == 3 and st.shape[0] >= 1
+        assert np.all(st[:, 0] <= st[:, 1]) and np.all(st[:, 1] <= st[:, 2])
+        bal = step3.balance(st, plan.step3_clock_hz())
+        say(f"  {st.shape[0]} chunks, imbalance {bal['imbalance']:.3f}")
+        assert 0.0 <= bal["imbalance"] < 1.0
