@@ -131,9 +131,15 @@ def cpu_baseline(workload, O=None, D=None, P=None, representation="csr"):
             "sample": f"{desc}: m={m} edges, one full oracle run of {dt:.2f} s on one host core"}
 
 
-def bench_batch(args):
-    """Batched + learned (one captured HIP graph, MLP-chosen parameters)
-    against plain per-graph launches (heuristic plans, one stream)."""
+def measure_batch(steps, warmup, with_autotune=True, check=True):
+    """The 512-graph uneven batch: plain per-graph launches (one heuristic
+    plan per graph, one stream) against one batched plan replayed from a
+    captured HIP graph, with the parameters chosen three ways: the heuristic,
+    the learned policy (MLP), and the autotuner's best configuration per
+    graph.  Returns a dict of times, speedups, plan times, the MLP's regret
+    against the autotuner, and output checks (plain against the oracle, every
+    batched variant against plain)."""
+    import concurrent.futures
     import torch
     import gen
     import paper_2501_06872_amd as gt
@@ -141,9 +147,8 @@ def bench_batch(args):
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    import concurrent.futures
     specs = gen.batch_specs(512, seed=5)
-    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool:  # the generator releases the GIL
+    with concurrent.futures.ThreadPoolExecutor(16) as pool:  # the generator releases the GIL
         host = list(pool.map(gen.from_spec, specs))
     m_total = sum(D.size for _, D, _ in host)
     n_total = sum(O.size - 1 for O, _, _ in host)
@@ -152,6 +157,18 @@ def bench_batch(args):
     graphs = [(torch.from_numpy(O).to(dev), torch.from_numpy(D).to(dev),
                torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None) for O, D, P in host]
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     # plain: one heuristic plan per graph, launches one graph after another
     shared = torch.empty(max(gt.workspace_bytes([g]) for g in graphs), dtype=torch.uint8, device=dev)
     tp = time.time()
@@ -163,54 +180,108 @@ def bench_batch(args):
         for p, g, o in zip(plains, graphs, outs_p):
             p.run(*g, out=o)
 
-    # batched + learned: one plan for all graphs, one captured HIP graph
-    model = mlp_model.DEFAULT_PATH
-    policy = gt.POLICY_MLP if os.path.exists(model) else gt.POLICY_HEURISTIC
+    run_plain()
+    torch.cuda.synchronize()
+    res = {"graphs": len(graphs), "n": n_total, "m": m_total}
+    if check:
+        import oracle
+
+        def ok(i):
+            O, D, P = host[i]
+            T, S, Q = outs_p[i]
+            rT, rS, rQ = oracle.transpose(O, D, P)
+            return (np.array_equal(T.cpu().numpy(), rT) and np.array_equal(S.cpu().numpy(), rS) and
+                    (P is None or np.array_equal(Q.cpu().numpy().view(np.uint32), rQ)))
+        tc = time.time()
+        with concurrent.futures.ThreadPoolExecutor(16) as pool:  # the oracle releases the GIL
+            res["plain_identical_to_oracle"] = bool(all(pool.map(ok, range(len(graphs)))))
+        print(f"[bench] batch512: plain outputs against the oracle in {time.time() - tc:.1f} s", file=sys.stderr,
+              flush=True)
+
+    # batched plans: heuristic, learned, autotuned; one workspace of the
+    # batch's any-parameter bound serves all three (they run one at a time)
+    ws_b = torch.empty(gt.workspace_bytes(graphs), dtype=torch.uint8, device=dev)
     tp = time.time()
-    bplan = gt.Plan(graphs, gt.make_options(policy=policy, model_path=model))
-    plan_batched_s = time.time() - tp
-    outs_b = [bplan.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(graphs)]
-    for _ in range(args.warmup):
+    b_heur = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_HEURISTIC), workspace=ws_b)
+    plan_heur_s = time.time() - tp
+    model = mlp_model.DEFAULT_PATH
+    tp = time.time()
+    b_mlp = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_MLP, model_path=model), workspace=ws_b)
+    plan_mlp_s = time.time() - tp
+    variants = [("heuristic", b_heur), ("mlp", b_mlp)]
+    regret = None
+    if with_autotune:
+        ta = time.time()
+        b_auto = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_FIXED), workspace=ws_b)
+        grid = [gt.config(c) for c in range(gt.num_configs())]
+        ratios = []
+        for i, g in enumerate(graphs):
+            at = gt.Plan([g], gt.make_options(policy=gt.POLICY_FIXED), workspace=shared)
+            ms, _ = gt.autotune(*g, reps=3, plan=at)
+            best = int(np.argmin(ms))
+            b_auto.set_config(i, best)
+            prm = b_mlp.params(i)
+            picked = [c for c, q in enumerate(grid) if q["fine_bits"] == prm["fine_bits"] and
+                      q["variant"] == prm["variant"] and q["digit_bits"] == prm["digit_bits"]]
+            if picked:
+                ratios.append(ms[picked[0]] / ms[best])
+        autotune_s = time.time() - ta
+        variants.append(("autotuned", b_auto))
+        if ratios:
+            regret = float(np.exp(np.mean(np.log(ratios))))
+        res["autotune_s"] = round(autotune_s, 2)
+        print(f"[bench] batch512: autotuned every graph in {autotune_s:.1f} s", file=sys.stderr, flush=True)
+    for _, p in variants:
+        assert p.workspace.data_ptr() == ws_b.data_ptr() and p.workspace_size() <= ws_b.numel()
+    outs_b = [b_mlp.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(graphs)]
+
+    for _ in range(warmup):
         run_plain()
-        bplan.run_batched(graphs, outs_b)
-    torch.cuda.synchronize()
-    hg = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(hg):
-        bplan.run_batched(graphs, outs_b)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        run_plain()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_plain = e0.elapsed_time(e1) / args.steps
-    e0.record(stream)
-    for _ in range(args.steps):
+    ms_plain = timed(run_plain, steps)
+    res["plain_ms"] = round(ms_plain, 4)
+    res["plain_ges"] = round(m_total / (ms_plain * 1e-3) / 1e9, 3)
+    for name, p in variants:
+        for _ in range(warmup):
+            p.run_batched(graphs, outs_b)
+        torch.cuda.synchronize()
+        hg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(hg):
+            p.run_batched(graphs, outs_b)
+        for T, S, Q in outs_b:  # scribble, so the replays must rewrite everything
+            T.fill_(-7)
+            S.fill_(-7)
         hg.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_batched = e0.elapsed_time(e1) / args.steps
-    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and
-               (a[2] is None or torch.equal(a[2], b[2])) for a, b in zip(outs_p, outs_b))
+        torch.cuda.synchronize()
+        same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and (a[2] is None or torch.equal(a[2], b[2]))
+                   for a, b in zip(outs_p, outs_b))
+        ms = timed(hg.replay, steps)
+        res[f"batched_{name}_ms"] = round(ms, 4)
+        res[f"batched_{name}_speedup"] = round(ms_plain / ms, 3)
+        res[f"batched_{name}_identical_to_plain"] = bool(same)
+        del hg
+    res["plan_s"] = {"plain_all_graphs": round(plan_plain_s, 4), "batched_heuristic": round(plan_heur_s, 4),
+                     "batched_mlp": round(plan_mlp_s, 4)}
+    res["speedup_incl_planning_mlp"] = round((ms_plain + plan_plain_s * 1e3) / (res["batched_mlp_ms"] +
+                                                                                 plan_mlp_s * 1e3), 3)
+    if regret is not None:
+        res["mlp_regret_vs_autotuner"] = round(regret, 4)
+    return res
+
+
+def bench_batch(args):
+    """--workload batch512: one JSON line whose value is the batched+learned
+    speedup over plain per-graph launches."""
+    r = measure_batch(args.steps, args.warmup, with_autotune=not args.no_autotune)
     res = {
         "metric": "batched+learned speedup over plain per-graph launches",
-        "value": round(ms_plain / ms_batched, 3),
+        "value": r["batched_mlp_speedup"],
         "unit": "x",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_batched, 4),
+        "ms_per_step": r["batched_mlp_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "batch512", "description": WORKLOADS["batch512"], "graphs": len(graphs),
-                   "n": n_total, "m": m_total, "policy": "mlp" if policy == gt.POLICY_MLP else "heuristic"},
-        "plain_ms": round(ms_plain, 4),
-        "batched_ms": round(ms_batched, 4),
-        "plain_ges": round(m_total / (ms_plain * 1e-3) / 1e9, 3),
-        "batched_ges": round(m_total / (ms_batched * 1e-3) / 1e9, 3),
-        "plan_s": {"plain": round(plan_plain_s, 3), "batched": round(plan_batched_s, 3)},
-        "end_to_end_speedup_incl_planning": round((ms_plain + plan_plain_s * 1e3) / (ms_batched + plan_batched_s * 1e3),
-                                                  3),
-        "outputs_identical": bool(same),
+        "config": {"workload": "batch512", "description": WORKLOADS["batch512"], "graphs": r["graphs"],
+                   "n": r["n"], "m": r["m"], "policy": "mlp"},
+        "batch512": r,
     }
     print(json.dumps(res), flush=True)
 
@@ -228,12 +299,20 @@ def main():
     ap.add_argument("--strategy", default="stable", choices=["stable", "hlh", "atomic", "probe"],
                     help="hlh / atomic: the paper's unordered methods (list order left to atomics); "
                          "probe: the one of the two that counts faster on a sample of the edges")
+    ap.add_argument("--hdv-max", type=int, default=0, help="hlh: at most this many HDVs (0: the Eq. 1 size, 8192)")
+    ap.add_argument("--step3", default="dispatch", choices=["dispatch", "static", "steal"],
+                    help="Step 3 of hlh / atomic: up to 2048 dispatched chunks, one static chunk per resident "
+                         "workgroup, or the two-phase scheme of Section V-F; static and steal also report the "
+                         "workgroup load imbalance of Step 3")
     ap.add_argument("--representation", default="csr", choices=["csr", "csc"],
                     help="csc: time the transposition of the workload's CSC form (the graph transposed once "
                          "on the GPU before timing), the CSC / CSC Rnd. inputs of the paper's evaluation")
     ap.add_argument("--coverage", action="store_true",
-                    help="report the share of edges into the 2048 most frequent destinations")
+                    help="report the share of edges into the 2048 and the 8192 most frequent destinations")
     ap.add_argument("--check", action="store_true", help="check the output on sampled vertex ranges")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-graph batch measurement that the default run appends (key batch512)")
+    ap.add_argument("--no-autotune", action="store_true", help="batch512 without the autotuned variant")
     ap.add_argument("--calibrate", action="store_true",
                     help="copy 1 GiB once before timing (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -267,16 +346,22 @@ def main():
     coverage = None
     if args.coverage:
         deg = np.bincount(D, minlength=n)
-        k = min(2048, n)
-        coverage = round(float(np.partition(deg, n - k)[n - k:].sum()) / max(m, 1), 4) if n else 0.0
+        coverage = {}
+        for kk in (2048, 8192):  # the HDV table's capacity before and after Eq. 1 sizing
+            k = min(kk, n)
+            coverage[f"top{kk}"] = round(float(np.partition(deg, n - k)[n - k:].sum()) / max(m, 1), 4) if n else 0.0
         del deg
     strategy = {"stable": gt.STRATEGY_STABLE, "hlh": gt.STRATEGY_HLH, "atomic": gt.STRATEGY_ATOMIC,
                 "probe": gt.STRATEGY_PROBE}[args.strategy]
-    opts = gt.make_options(strategy=strategy)
+    flags = {"dispatch": 0, "static": gt.FLAG_STEP3_STATIC | gt.FLAG_STEP3_TIMES,
+             "steal": gt.FLAG_STEP3_STEAL | gt.FLAG_STEP3_TIMES}[args.step3] if args.strategy != "stable" else 0
+    opts = gt.make_options(strategy=strategy, flags=flags, hdv_max=args.hdv_max)
     if args.fine_bits or args.digit_bits or args.variant:
         opts = gt.make_options(policy=gt.POLICY_FIXED, fine_bits=args.fine_bits, digit_bits=args.digit_bits,
-                               variant=args.variant, strategy=strategy)
+                               variant=args.variant, strategy=strategy, flags=flags, hdv_max=args.hdv_max)
+    tp = time.perf_counter()
     plan = gt.Plan([(O_t, D_t, P_t)], opts)
+    plan_ms = (time.perf_counter() - tp) * 1e3
     params = plan.params()
     params["packed"] = plan.packed()
     resolved = {gt.STRATEGY_STABLE: "stable", gt.STRATEGY_HLH: "hlh", gt.STRATEGY_ATOMIC: "atomic"}[plan.strategy()]
@@ -308,6 +393,10 @@ def main():
     plan.profile(False)
     if plan.device_status() != 0:
         raise SystemExit("device reported an invalid graph")
+    step3_balance = None
+    if flags and plan.strategy() != gt.STRATEGY_STABLE:
+        from paper_2501_06872_amd import step3
+        step3_balance = step3.balance(plan.step3_times(), plan.step3_clock_hz())  # the last timed step
     ms = total_ms / args.steps
     ges = m / (ms * 1e-3) / 1e9
 
@@ -363,6 +452,7 @@ def main():
                    "payload_bytes": w, "representation": args.representation, "strategy": args.strategy,
                    "strategy_run": resolved,
                    "params": params if args.strategy == "stable" else None},
+        "plan_ms": round(plan_ms, 3),
         "path_hbm_frac": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "path_alg_bytes": b_alg,
         "kernel_ms": kernels,
@@ -379,11 +469,19 @@ def main():
     }
     if check is not None:
         res["check_sampled_slices"] = check
+    if step3_balance is not None:
+        res["config"]["step3"] = args.step3
+        res["step3_balance"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in step3_balance.items()}
     if coverage is not None:
-        res["config"]["coverage_top2048"] = coverage
+        res["config"]["coverage"] = coverage
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(args.workload, O, D, P, args.representation)
+    if not args.no_batch:
+        # the batched + learned target, measured in the same run
+        del O_t, D_t, P_t, out, plan
+        torch.cuda.empty_cache()
+        res["batch512"] = measure_batch(5, 2, with_autotune=not args.no_autotune)
     print(json.dumps(res), flush=True)
 
 

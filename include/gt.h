@@ -99,7 +99,7 @@ typedef struct {
   const char *model_path;/* weights of the learned policy (GT_POLICY_MLP) */
   int32_t flags;         /* GT_FLAG_* */
   int32_t strategy;      /* GT_STRATEGY_* (0 = the stable method) */
-  int32_t hdv_max;       /* GT_STRATEGY_HLH: at most this many HDVs (0 = 2048, the maximum) */
+  int32_t hdv_max;       /* GT_STRATEGY_HLH: at most this many HDVs (0 = 8192, the maximum: Eq. 1 on 160 KB of LDS) */
 } gt_options_t;
 
 /* Strategies.  GT_STRATEGY_STABLE (the default) produces every CSC list in

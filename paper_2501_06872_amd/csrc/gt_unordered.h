@@ -6,8 +6,15 @@
 
 namespace gt {
 
-constexpr int kHlhMaxHdv = 2048;    // HDVs held in LDS per workgroup
-constexpr int kHlhLog2Slots = 12;   // table slots (load factor <= 1/2)
+// HDVs held in LDS per workgroup, sized by Eq. 1 (Section IV-A):
+// k = |cache| / (|r| / alpha + d * t) with the 160 KB LDS of one compute unit
+// as the cache (one workgroup per compute unit), |r| = 6 bytes per table slot
+// (vertex ID + HDV index), alpha = 1/2, d = 2 bytes (16-bit low counter),
+// t = 1 counter set per workgroup: 160 KB / 14 B = 11.7K, of which the
+// largest power of two, 8192, is used (112 KB of Step 1's LDS; Step 3 holds
+// 32-bit cursors instead, 144 KB).
+constexpr int kHlhMaxHdv = 8192;
+constexpr int kHlhLog2Slots = 14;   // table slots (load factor <= 1/2)
 constexpr int kHdvHistBins = 4096;  // sampled frequencies, capped
 
 struct UnorderedArgs {

@@ -28,8 +28,10 @@ namespace gt {
 
 namespace {
 
-constexpr int kUNT = 256;  // threads per workgroup of the count / scatter kernels
-constexpr int kUTile = kUNT * 16;  // edges per source-staging tile of the scatter
+// threads per workgroup of the count / scatter kernels: one workgroup per
+// compute unit (the HDV table fills most of its LDS)
+constexpr int kUNT = 1024;
+constexpr int kUTile = 4096;  // edges per source-staging tile of the scatter
 
 __device__ __forceinline__ uint32_t hdv_hash(uint32_t v, int log2slots) {
   return (v * 0x9E3779B1u) >> (32 - log2slots);
@@ -118,6 +120,27 @@ __device__ __forceinline__ void part_range(const UnorderedArgs &a, int64_t c, in
   hi = hend + tl * part / nt;
 }
 
+// Step 1's HDV counters (Algorithm 2, the narrow private counters): a 16-bit
+// low counter per HDV, two per 32-bit LDS word, updated by compare-and-swap
+// so that no carry reaches the neighbouring counter.  A low counter that
+// wraps adds one to the HDV's high counter of the part, `high[h]` in global
+// memory (once per 65536 edges of one HDV in one part).
+__device__ __forceinline__ void hdv_count16(uint32_t *low, uint32_t h, uint32_t len, uint32_t *high) {
+  uint32_t *wp = low + (h >> 1);
+  const int sh = (int)(h & 1u) * 16;
+  uint32_t old = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (true) {
+    const uint32_t sum = ((old >> sh) & 0xFFFFu) + len;  // len <= 64
+    const uint32_t nw = (old & ~(0xFFFFu << sh)) | ((sum & 0xFFFFu) << sh);
+    const uint32_t seen = atomicCAS(wp, old, nw);
+    if (seen == old) {
+      if (sum >> 16) atomicAdd(high + h, 1u);
+      return;
+    }
+    old = seen;
+  }
+}
+
 }  // namespace
 
 // Step 0 (selection): histogram of sampled frequencies >= 2 (capped).
@@ -153,19 +176,24 @@ __global__ __launch_bounds__(256) void k_hdv_compact(const int32_t *keys, const 
 }
 
 // Step 1: in-degrees.  Workgroup c owns edges [c*chunk, (c+1)*chunk); the
-// HDV counts of every part of the chunk go to a row of their own.
+// HDV counts of every part of the chunk go to a row of their own.  During a
+// part the row holds the high counters (zeroed first); at the part's end it
+// receives high * 65536 + low.
 __global__ __launch_bounds__(kUNT) void k_hlh_count(UnorderedArgs a) {
   __shared__ int32_t s_key[1 << kHlhLog2Slots];
   __shared__ uint16_t s_idx[1 << kHlhLog2Slots];
-  __shared__ uint32_t s_cnt[kHlhMaxHdv];
+  __shared__ uint32_t s_low[kHlhMaxHdv / 2];  // 16-bit low counters, two per word
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   HdvTable tab{s_key, s_idx, a.log2slots, 0};
   const uint32_t nh = a.nhdv ? *a.nhdv : 0u;
-  for (uint32_t h = tid; h < nh; h += kUNT) s_cnt[h] = 0u;
+  for (uint32_t i = tid; i < (nh + 1) / 2; i += kUNT) s_low[i] = 0u;
   tab.build(a.hdv, nh, tid, kUNT);
   const uint32_t un = (uint32_t)a.n;
   bool bad = false;
   for (int part = 0; part < a.nparts; ++part) {
+    uint32_t *row = a.H + ((int64_t)blockIdx.x * a.nparts + part) * a.kmax;
+    for (uint32_t h = tid; h < nh; h += kUNT) row[h] = 0u;  // high counters of the part
+    __syncthreads();
     int64_t beg, end;
     part_range(a, blockIdx.x, part, beg, end);
     for (int64_t base = beg; base < end; base += kUNT) {
@@ -177,17 +205,17 @@ __global__ __launch_bounds__(kUNT) void k_hlh_count(UnorderedArgs a) {
       const Run r = lane_runs(v, ok, lane);
       if (r.head) {
         const int h = tab.find(v);
-        if (h >= 0) atomicAdd(&s_cnt[h], r.len);
+        if (h >= 0) hdv_count16(s_low, (uint32_t)h, r.len, row);
         else atomicAdd(&a.cnt[v], r.len);
       }
     }
     __syncthreads();
-    uint32_t *row = a.H + ((int64_t)blockIdx.x * a.nparts + part) * a.kmax;
     for (uint32_t h = tid; h < nh; h += kUNT) {
-      row[h] = s_cnt[h];
-      s_cnt[h] = 0u;
+      const uint32_t hi = __hip_atomic_load(row + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      row[h] = (hi << 16) + ((s_low[h >> 1] >> ((h & 1u) * 16)) & 0xFFFFu);
     }
     __syncthreads();
+    for (uint32_t i = tid; i < (nh + 1) / 2; i += kUNT) s_low[i] = 0u;
   }
   if (bad) atomicOr(a.err, kErrBadIndex);
 }
@@ -261,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_scan_offsets(UnorderedArgs a) {
 // Step 3, one part [beg, end) whose HDV ranges start at row `row` of H:
 // tiles of kUTile edges whose sources are derived from the offsets in LDS.
 struct ScatterLds {
-  unsigned long long *cur;  // [kHlhMaxHdv] HDV cursors
+  uint32_t *cur;            // [kHlhMaxHdv] HDV cursors, relative to the part's HDV range
   uint32_t *src;            // [kUTile]
   uint32_t *wmax;           // [kUNT / kWave]
   int64_t *u0;
@@ -271,8 +299,8 @@ __device__ void scatter_part(const UnorderedArgs &a, const HdvTable &tab, uint32
                              int64_t end, const ScatterLds &l) {
   constexpr int ITEMS = kUTile / kUNT;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  for (uint32_t h = tid; h < nh; h += kUNT)
-    l.cur[h] = (unsigned long long)a.T[a.hdv[h]] + a.H[row * a.kmax + h];
+  for (uint32_t h = tid; h < nh; h += kUNT) l.cur[h] = 0u;
+  const uint32_t *hrow = a.H + row * a.kmax;  // HDV h's range of this part starts at T[hdv[h]] + hrow[h]
   if (tid == 0) {  // source of the part's first edge: the largest u with O[u] <= beg
     int64_t lo = 0, hi = a.n;
     while (hi - lo > 1) {
@@ -320,7 +348,7 @@ __device__ void scatter_part(const UnorderedArgs &a, const HdvTable &tab, uint32
       unsigned long long pos0 = 0;
       if (run.head) {
         const int h = tab.find(v);
-        pos0 = h >= 0 ? atomicAdd(&l.cur[h], (unsigned long long)run.len)
+        pos0 = h >= 0 ? (unsigned long long)a.T[v] + hrow[h] + atomicAdd(&l.cur[h], run.len)
                       : atomicAdd(&a.cur[v], (unsigned long long)run.len);
       }
       const unsigned long long pos = __shfl(pos0, run.head_lane) + (unsigned long long)(lane - run.head_lane);
@@ -347,7 +375,7 @@ __device__ void scatter_part(const UnorderedArgs &a, const HdvTable &tab, uint32
 __global__ __launch_bounds__(kUNT) void k_hlh_scatter(UnorderedArgs a) {
   __shared__ int32_t s_key[1 << kHlhLog2Slots];
   __shared__ uint16_t s_idx[1 << kHlhLog2Slots];
-  __shared__ unsigned long long s_cur[kHlhMaxHdv];
+  __shared__ uint32_t s_cur[kHlhMaxHdv];
   __shared__ uint32_t s_src[kUTile];
   __shared__ uint32_t s_wmax[kUNT / kWave];
   __shared__ int64_t s_u0;

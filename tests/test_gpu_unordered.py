@@ -171,3 +171,26 @@ def test_step3_time_stamps(hip_device):
         bal = step3.balance(st, plan.step3_clock_hz())
         say(f"  {st.shape[0]} chunks, imbalance {bal['imbalance']:.3f}")
         assert 0.0 <= bal["imbalance"] < 1.0
+
+
+def test_hlh_sixteen_bit_counters_carry(hip_device):
+    """Step 1's HDV counters are 16-bit with a carry into the part's high
+    counter (Algorithm 2): a hub whose edges fill whole chunks wraps its low
+    counter exactly once per chunk (2^20 edges: 16 chunks of 65536) and twice
+    per chunk when chunks hold 2^17 edges (2^25 edges in the static
+    chunking: one chunk per resident workgroup).  The offsets stay exact and
+    every list equals the oracle's as a multiset."""
+    import paper_2501_06872_amd as gt
+    for m, flags in ((1 << 20, 0), (1 << 25, gt.FLAG_STEP3_STATIC)):
+        n = 1 << 20
+        O = np.arange(0, m + 1, m // n, dtype=np.int64)
+        D = np.full(m, 12345, dtype=np.int32)
+        D[::1001] = np.arange(D[::1001].size, dtype=np.int32) % n  # a few other destinations
+        for u in range(0, n, max(1, n // 4096)):
+            D[O[u]:O[u + 1]].sort()
+        if m == 1 << 20:
+            P = np.arange(m, dtype=np.uint32)
+        else:
+            P = None
+        # lists must ascend for the generator's reading, not for the method
+        assert_unordered_parity(O, D, P, hip_device, f"hub m=2^{m.bit_length() - 1}", "hlh", flags=flags)
