@@ -209,6 +209,16 @@ def measure_batch(steps, warmup, with_autotune=True, check=True):
     b_mlp = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_MLP, model_path=model), workspace=ws_b)
     plan_mlp_s = time.time() - tp
     variants = [("heuristic", b_heur), ("mlp", b_mlp)]
+    # the same choices run by the persistent kernel (one launch drains a work
+    # queue of every graph's phases; variant-1 tiles, digits of <= 9 bits)
+    tp = time.time()
+    p_heur = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_HEURISTIC, flags=gt.FLAG_PERSISTENT), workspace=ws_b)
+    plan_pheur_s = time.time() - tp
+    tp = time.time()
+    p_mlp = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_MLP, model_path=model, flags=gt.FLAG_PERSISTENT),
+                    workspace=ws_b)
+    plan_pmlp_s = time.time() - tp
+    variants += [("persistent_heuristic", p_heur), ("persistent_mlp", p_mlp)]
     regret = None
     if with_autotune:
         ta = time.time()
@@ -260,7 +270,8 @@ def measure_batch(steps, warmup, with_autotune=True, check=True):
         res[f"batched_{name}_identical_to_plain"] = bool(same)
         del hg
     res["plan_s"] = {"plain_all_graphs": round(plan_plain_s, 4), "batched_heuristic": round(plan_heur_s, 4),
-                     "batched_mlp": round(plan_mlp_s, 4)}
+                     "batched_mlp": round(plan_mlp_s, 4), "persistent_heuristic": round(plan_pheur_s, 4),
+                     "persistent_mlp": round(plan_pmlp_s, 4)}
     res["speedup_incl_planning_mlp"] = round((ms_plain + plan_plain_s * 1e3) / (res["batched_mlp_ms"] +
                                                                                  plan_mlp_s * 1e3), 3)
     if regret is not None:

@@ -55,7 +55,8 @@ typedef enum {
   GT_ERR_WORKSPACE_TOO_SMALL = 3,
   GT_ERR_UNSUPPORTED = 4,        /* a parameter outside the compiled kernel variants, or m > 2^32 */
   GT_ERR_HIP = 5,                /* a HIP runtime call failed */
-  GT_ERR_COUNTER_OVERFLOW = 6    /* device-detected: counts that do not add up to m (a wrapped counter) */
+  GT_ERR_COUNTER_OVERFLOW = 6,   /* device-detected: counts that do not add up to m (a wrapped counter) */
+  GT_ERR_STALLED = 7             /* device-detected: a wait of the persistent batched kernel gave up */
 } gt_status;
 
 /* Largest edge count accepted (GT_ERR_UNSUPPORTED above it): with m <= 2^32
@@ -142,8 +143,14 @@ enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2, GT_S
  * places its HDV edges through LDS cursors.  GT_FLAG_STEP3_TIMES records
  * per-chunk wall-clock stamps of Step 3 (gt_plan_step3_times).  The output
  * does not depend on these flags beyond the order the atomics give. */
+/* GT_FLAG_PERSISTENT: gt_transpose_batched runs the whole batch as one
+ * persistent kernel launch (see there).  Its bodies take variant-1 tiles and
+ * digits of at most 9 bits, so the plan's choice of every graph is adjusted
+ * to that (gt_plan_set_config's too); gt_plan returns GT_ERR_UNSUPPORTED for
+ * a graph that still does not fit (more than two partition passes, m >= 2^31,
+ * GT_FLAG_WIDE_STATUS, an unordered strategy). */
 enum { GT_FLAG_WIDE_STATUS = 1, GT_FLAG_FEATURES = 2, GT_FLAG_STEP3_STATIC = 4, GT_FLAG_STEP3_STEAL = 8,
-       GT_FLAG_STEP3_TIMES = 16 };
+       GT_FLAG_STEP3_TIMES = 16, GT_FLAG_PERSISTENT = 32 };
 
 typedef struct gt_plan_st *gt_plan_t;
 
@@ -204,11 +211,22 @@ gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *w
                        size_t workspace_bytes, void *stream);
 
 /* Transpose `count` graphs (each as gt_transpose) for a plan built for the
- * same count and sizes.  The kernels of different graphs run on the plan's
- * internal streams (forked from `stream` by one event and joined back by one
- * event per stream), so the whole call is one asynchronous, capturable
- * launch sequence on `stream`.  graphs / outs: host arrays of `count`
- * descriptors.  Errors as gt_transpose. */
+ * same count and sizes.  graphs / outs: host arrays of `count` descriptors.
+ * The call is one asynchronous, capturable launch sequence on `stream`.
+ * Default: the kernels of different graphs run on the plan's internal
+ * streams (forked from `stream` by one event and joined back by one event
+ * per stream).  GT_FLAG_PERSISTENT plans: one copy of the graph descriptors
+ * and the phase table from the plan's pinned staging buffer into the
+ * workspace, one clear of the queue counters, then one launch of the
+ * persistent kernel, whose resident workgroups take (graph, phase, item)
+ * tickets from one device counter and run every phase of every graph in
+ * dependency order (Section V-F's dynamic work distribution, over the whole
+ * batch).  The call waits (on the host) for the previous call's copy out of
+ * the staging buffer unless `stream` is being captured; a captured batch
+ * copies the staging buffer's contents at replay, so a plan whose batch is
+ * captured must not be run eagerly with other buffers between replays.
+ * Errors as gt_transpose; a wait of the persistent kernel that gives up is
+ * reported as GT_ERR_STALLED by gt_plan_device_status(). */
 gt_status gt_transpose_batched(gt_plan_t plan, int32_t count, const gt_csr_t *graphs, gt_csc_t *outs,
                                void *workspace, size_t workspace_bytes, void *stream);
 
@@ -246,7 +264,9 @@ gt_status gt_transpose_noalloc(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out,
  * last transposition run with this plan in `workspace`.  GT_OK;
  * GT_ERR_INVALID_GRAPH if an index lies outside [0, n) or (with validation)
  * the offsets are not nondecreasing from 0 to m; GT_ERR_COUNTER_OVERFLOW if
- * a count did not add up (see GT_MAX_EDGES).  Reads 4 bytes of the workspace
+ * a count did not add up (see GT_MAX_EDGES); GT_ERR_STALLED if a dependency
+ * wait of the persistent batched kernel gave up (after seconds; the output is
+ * then undefined).  Reads 4 bytes of the workspace
  * with a blocking copy.  Errors: GT_ERR_INVALID_ARGUMENT (NULL plan or
  * workspace), GT_ERR_HIP. */
 gt_status gt_plan_device_status(gt_plan_t plan, const void *workspace);

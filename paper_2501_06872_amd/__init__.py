@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgt.so")
 
 (GT_OK, GT_ERR_INVALID_ARGUMENT, GT_ERR_INVALID_GRAPH, GT_ERR_WORKSPACE_TOO_SMALL, GT_ERR_UNSUPPORTED, GT_ERR_HIP,
- GT_ERR_COUNTER_OVERFLOW) = range(7)
+ GT_ERR_COUNTER_OVERFLOW, GT_ERR_STALLED) = range(8)
 MAX_EDGES = 1 << 32
 NOALLOC_SCRATCH_BYTES = 64 << 20  # the library's own scratch per GPU (gt_transpose_noalloc)
 POLICY_HEURISTIC, POLICY_FIXED, POLICY_MLP = range(3)
@@ -140,7 +140,7 @@ def _check_inputs(offsets, indices, payload):
             raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
 
 
-FLAG_WIDE_STATUS, FLAG_FEATURES, FLAG_STEP3_STATIC, FLAG_STEP3_STEAL, FLAG_STEP3_TIMES = 1, 2, 4, 8, 16
+FLAG_WIDE_STATUS, FLAG_FEATURES, FLAG_STEP3_STATIC, FLAG_STEP3_STEAL, FLAG_STEP3_TIMES, FLAG_PERSISTENT = 1, 2, 4, 8, 16, 32
 
 
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,

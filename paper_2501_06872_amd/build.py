@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["gt_api.hip", "gt_kernels.hip", "gt_policy.hip", "gt_sample.hip", "gt_mlp.hip", "gt_unordered.hip",
+SOURCES = ["gt_api.hip", "gt_kernels.hip", "gt_persistent.hip", "gt_policy.hip", "gt_sample.hip", "gt_mlp.hip", "gt_unordered.hip",
            "gt_microbench.hip"]
 LIB = os.path.join(HERE, "libgt.so")
 OBJDIR = os.path.join(HERE, "_build")
@@ -27,9 +27,15 @@ def _filtered(r):
     return [l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops' is not a recognized" not in l]
 
 
+# per-source flags: the persistent kernel runs every body inside one loop;
+# without machine-level loop-invariant code motion the compiler keeps no
+# body's constants live across the others
+EXTRA_FLAGS = {"gt_persistent.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(OBJDIR, os.path.splitext(os.path.basename(src))[0] + ".o")
-    cmd = [HIPCC] + HIPCC_FLAGS + ["-c", "-o", obj, src]
+    cmd = [HIPCC] + HIPCC_FLAGS + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", "-o", obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -215,6 +215,40 @@ void finalize_params(GraphPlan &p, size_t base) {
   p.ws_end = off;
 }
 
+size_t persist_counters_end(int32_t count) {
+  return kPersistDoneOff + 4 * (size_t)count * kPersistMaxPhases;
+}
+
+size_t persist_tables_bytes(int32_t count) {
+  return align_up(sizeof(StableLaunch) * (size_t)count) +
+         align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases);
+}
+
+void persist_coerce(GraphPlan &p) {
+  p.variant = 1;
+  p.digit_bits = std::min(p.digit_bits, 9);
+}
+
+bool persist_eligible(const GraphPlan &p) {
+  if (p.strategy != GT_STRATEGY_STABLE) return false;
+  if (p.n == 0 || p.m == 0) return true;
+  return p.variant == 1 && p.tile == lsd_tile_size(1) && p.max_bits <= 9 && p.passes <= 2 && !p.wide_status;
+}
+
+void layout_plan(gt_plan_st *plan) {
+  size_t base = plan->persistent ? align_up(persist_counters_end(plan->count)) : kAlign;  // byte 0: status word
+  for (GraphPlan &p : plan->graphs) {
+    finalize_params(p, base);
+    base = align_up(p.ws_end);
+  }
+  if (plan->persistent) {
+    plan->off_pdesc = base;
+    plan->off_pphase = base + align_up(sizeof(StableLaunch) * (size_t)plan->count);
+    base += persist_tables_bytes(plan->count);
+  }
+  plan->ws_bytes = std::max<size_t>(base, 256);
+}
+
 // Largest workspace any policy can need for one graph.
 size_t graph_workspace_bound(int64_t n, int64_t m, bool pay) {
   size_t best = 0;
@@ -260,6 +294,102 @@ hipError_t Profiler::end(hipStream_t st) {
   return hipEventRecord(recs.back().stop, st);
 }
 
+// The arguments of every kernel of a stable transposition.
+StableLaunch stable_launch(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate) {
+  StableLaunch L{};
+  L.O = g.offsets; L.D = g.indices; L.n = p.n; L.m = p.m;
+  L.ntiles = p.ntiles; L.tile = p.tile; L.nbins_total = p.nbins_total;
+  L.passes = p.passes; L.radix0 = 1 << p.bits[0]; L.variant = p.variant;
+  L.pay = p.pay; L.wide = p.wide_status; L.validate = validate;
+  L.err = reinterpret_cast<uint32_t *>(ws);
+  L.ticket = reinterpret_cast<uint32_t *>(ws + p.off_ticket);
+  L.part = reinterpret_cast<uint32_t *>(ws + p.off_part);
+  L.digit = reinterpret_cast<uint64_t *>(ws + p.off_digit);
+  L.bins = reinterpret_cast<uint64_t *>(ws + p.off_bin);
+  L.status = reinterpret_cast<uint32_t *>(ws + p.off_status);
+  L.status_words = (uint64_t)p.ntiles * ((uint64_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
+  L.tsrc = reinterpret_cast<int32_t *>(ws + p.off_tsrc);
+  L.tcnt = reinterpret_cast<uint16_t *>(ws + p.off_tcnt);
+  L.tbsum = reinterpret_cast<uint32_t *>(ws + p.off_tbsum);
+  L.toff = reinterpret_cast<uint32_t *>(ws + p.off_toff);
+  L.dtot = reinterpret_cast<uint64_t *>(ws + p.off_dtot);
+  L.h.passes = p.passes;
+  for (int i = 0; i < p.passes; ++i) { L.h.shift[i] = p.shift[i]; L.h.bits[i] = p.bits[i]; }
+  // histogram workgroups take contiguous ranges of the first pass's tiles,
+  // at most kHistBlocks of them: a small graph neither launches nor sums
+  // partial histograms it has no edges for
+  L.hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles));
+  const int32_t *cur_src = nullptr;
+  const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
+  for (int pass = 0; pass < p.passes; ++pass) {
+    const bool first = pass == 0, last = pass == p.passes - 1;
+    LsdArgs &a = L.lsd[pass];
+    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = L.tsrc; a.tile_off = L.toff;
+    a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
+    const bool pk = p.packed && (first != last);
+    L.pk[pass] = pk;
+    if (pk && last) a.in_key16 = reinterpret_cast<const uint16_t *>(cur_key);
+    if (last) {
+      a.out_src = reinterpret_cast<int32_t *>(ws + p.off_b_src);
+      a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_b_key);
+      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + p.off_b_pay) : nullptr;
+    } else {
+      const bool use_a2 = (pass == 1);
+      a.out_src = reinterpret_cast<int32_t *>(ws + (use_a2 ? p.off_a2_src : p.off_a_src));
+      a.out_key32 = reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_key : p.off_a_key));
+      if (pk) a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_a_key);
+      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_pay : p.off_a_pay)) : nullptr;
+    }
+    a.shift = p.shift[pass];
+    a.bits = p.bits[pass];
+    a.digit_start = L.digit + pass * (kMaxRadix + 1);
+    a.status = L.status;
+    a.ticket = L.ticket + pass;
+    a.m = p.m; a.n = p.n;
+    a.fine_shift = p.fine_bits;
+    a.lower_bits = p.total_bits - p.bits[p.passes - 1];
+    a.fine_mask = (1u << p.fine_bits) - 1u;
+    a.bin_start = L.bins;
+    if (pk) {
+      a.pk_lo = 16 - p.bits[1];
+      a.pk_src_bits = p.id_bits;
+      a.pk_dshift = p.shift[1];
+      a.pk_dbits = p.bits[1];
+      if (last) {  // the packed key holds the digit at bit pk_lo
+        a.shift = a.pk_lo;
+        a.prev_digit_start = L.digit;
+        a.prev_bits = p.bits[0];
+      }
+    }
+    cur_src = a.out_src;
+    cur_key = a.out_key32;
+    cur_pay = a.out_pay;
+  }
+  FinalArgs &f = L.f;
+  f.in_src = reinterpret_cast<const int32_t *>(ws + p.off_b_src);
+  f.in_key = reinterpret_cast<const uint16_t *>(ws + p.off_b_key);
+  f.in_pay = p.pay ? reinterpret_cast<const uint32_t *>(ws + p.off_b_pay) : nullptr;
+  f.bin_start = L.bins;
+  f.T = out.offsets; f.S = out.indices; f.Q = out.payload;
+  f.n = p.n; f.m = p.m; f.nbins = p.nbins; f.fine_bits = p.fine_bits;
+  f.nch = reinterpret_cast<uint32_t *>(ws + p.off_nch);
+  f.item_base = reinterpret_cast<uint32_t *>(ws + p.off_ibase);
+  f.item_desc = reinterpret_cast<uint4 *>(ws + p.off_ibin);
+  f.total_items = reinterpret_cast<uint32_t *>(ws + p.off_itotal);
+  f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
+  f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
+  f.nbig = f.total_items + 2;
+  f.hugebins = reinterpret_cast<uint32_t *>(ws + p.off_huge);
+  f.nhuge = f.total_items + 3;
+  f.err = L.err;
+  L.sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
+  L.scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
+  L.max_items = p.max_items;
+  L.max_big = p.max_big;
+  L.max_huge = p.max_huge;
+  return L;
+}
+
 // Enqueue the whole transposition of one graph.
 gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
                         bool reset_status, Profiler *prof, hipStream_t st) {
@@ -277,108 +407,32 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   if (validate) GT_CHK(launch_validate_offsets(g.offsets, p.n, p.m, err, st));
   if (p.strategy != GT_STRATEGY_STABLE) return enqueue_unordered(p, g, out, ws, prof, st);
 
-  uint32_t *ticket = reinterpret_cast<uint32_t *>(ws + p.off_ticket);
-  uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
-  uint64_t *digit = reinterpret_cast<uint64_t *>(ws + p.off_digit);
-  uint64_t *bins = reinterpret_cast<uint64_t *>(ws + p.off_bin);
-  void *status = ws + p.off_status;
-  int32_t *tsrc = reinterpret_cast<int32_t *>(ws + p.off_tsrc);
-
-  HistArgs h{};
-  h.passes = p.passes;
-  for (int i = 0; i < p.passes; ++i) { h.shift[i] = p.shift[i]; h.bits[i] = p.bits[i]; }
-  // histogram workgroups take contiguous ranges of the first pass's tiles,
-  // at most kHistBlocks of them: a small graph neither launches nor sums
-  // partial histograms it has no edges for
-  const int hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles));
-  uint16_t *tcnt = reinterpret_cast<uint16_t *>(ws + p.off_tcnt);
-  uint32_t *toff = reinterpret_cast<uint32_t *>(ws + p.off_toff);
-  uint64_t *dtot = reinterpret_cast<uint64_t *>(ws + p.off_dtot);
-  GT_TIMED("k_hist", launch_hist(g.indices, p.m, p.n, h, p.tile, p.ntiles, hist_blocks, part, tcnt, err, st));
-  GT_TIMED("k_tile_scan", launch_tile_scan(tcnt, p.ntiles, 1 << p.bits[0],
-                                           reinterpret_cast<uint32_t *>(ws + p.off_tbsum), dtot, toff, st));
-  GT_TIMED("k_digit_scan", launch_digit_scan(part, hist_blocks, h, dtot, digit, bins, p.nbins_total, p.m, err, st));
-  GT_TIMED("k_tile_src", launch_tile_src(g.offsets, p.n, p.m, p.tile, p.ntiles, tsrc, st));
-
-  const size_t status_words = (size_t)p.ntiles * ((size_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
-  const int32_t *cur_src = nullptr;
-  const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
-  for (int pass = 0; pass < p.passes; ++pass) {
-    const bool first = pass == 0, last = pass == p.passes - 1;
+  const StableLaunch L = stable_launch(p, g, out, ws, validate);
+  GT_TIMED("k_hist", launch_hist(L.D, L.m, L.n, L.h, L.tile, L.ntiles, L.hist_blocks, L.part, L.tcnt, L.err, st));
+  GT_TIMED("k_tile_scan", launch_tile_scan(L.tcnt, L.ntiles, L.radix0, L.tbsum, L.dtot, L.toff, st));
+  GT_TIMED("k_digit_scan", launch_digit_scan(L.part, L.hist_blocks, L.h, L.dtot, L.digit, L.bins, L.nbins_total,
+                                             L.m, L.err, st));
+  GT_TIMED("k_tile_src", launch_tile_src(L.O, L.n, L.m, L.tile, L.ntiles, L.tsrc, st));
+  for (int pass = 0; pass < L.passes; ++pass) {
+    const bool first = pass == 0, last = pass == L.passes - 1;
     if (!first) {  // the first pass places its tiles with k_hist's tile offsets
-      GT_TIMED("k_fill_status", launch_fill(static_cast<uint32_t *>(status), status_words, 0u, st));
-      GT_CHK(launch_fill(ticket + pass, 1, 0u, st));
-    }
-    LsdArgs a{};
-    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = tsrc; a.tile_off = toff;
-    a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
-    const bool pk = p.packed && (first != last);
-    if (pk && last) a.in_key16 = reinterpret_cast<const uint16_t *>(cur_key);
-    if (last) {
-      a.out_src = reinterpret_cast<int32_t *>(ws + p.off_b_src);
-      a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_b_key);
-      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + p.off_b_pay) : nullptr;
-    } else {
-      const bool use_a2 = (pass == 1);
-      a.out_src = reinterpret_cast<int32_t *>(ws + (use_a2 ? p.off_a2_src : p.off_a_src));
-      a.out_key32 = reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_key : p.off_a_key));
-      if (pk) a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_a_key);
-      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_pay : p.off_a_pay)) : nullptr;
-    }
-    a.shift = p.shift[pass];
-    a.bits = p.bits[pass];
-    a.digit_start = digit + pass * (kMaxRadix + 1);
-    a.status = status;
-    a.ticket = ticket + pass;
-    a.m = p.m; a.n = p.n;
-    a.fine_shift = p.fine_bits;
-    a.lower_bits = p.total_bits - p.bits[p.passes - 1];
-    a.fine_mask = (1u << p.fine_bits) - 1u;
-    a.bin_start = bins;
-    if (pk) {
-      a.pk_lo = 16 - p.bits[1];
-      a.pk_src_bits = p.id_bits;
-      a.pk_dshift = p.shift[1];
-      a.pk_dbits = p.bits[1];
-      if (last) {  // the packed key holds the digit at bit pk_lo
-        a.shift = a.pk_lo;
-        a.prev_digit_start = digit;
-        a.prev_bits = p.bits[0];
-      }
+      GT_TIMED("k_fill_status", launch_fill(L.status, L.status_words, 0u, st));
+      GT_CHK(launch_fill(L.ticket + pass, 1, 0u, st));
     }
     static const char *kLsdNames[kMaxPasses] = {"k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2"};
-    GT_TIMED(kLsdNames[pass], launch_lsd(p.variant, p.bits[pass], a, first, p.pay, last, pk, p.wide_status, st));
-    cur_src = a.out_src;
-    cur_key = a.out_key32;
-    cur_pay = a.out_pay;
+    GT_TIMED(kLsdNames[pass], launch_lsd(L.variant, p.bits[pass], L.lsd[pass], first, L.pay, last, L.pk[pass], L.wide,
+                                         st));
   }
-  FinalArgs f{};
-  f.in_src = reinterpret_cast<const int32_t *>(ws + p.off_b_src);
-  f.in_key = reinterpret_cast<const uint16_t *>(ws + p.off_b_key);
-  f.in_pay = p.pay ? reinterpret_cast<const uint32_t *>(ws + p.off_b_pay) : nullptr;
-  f.bin_start = bins;
-  f.T = out.offsets; f.S = out.indices; f.Q = out.payload;
-  f.n = p.n; f.m = p.m; f.nbins = p.nbins; f.fine_bits = p.fine_bits;
-  f.nch = reinterpret_cast<uint32_t *>(ws + p.off_nch);
-  f.item_base = reinterpret_cast<uint32_t *>(ws + p.off_ibase);
-  f.item_desc = reinterpret_cast<uint4 *>(ws + p.off_ibin);
-  f.total_items = reinterpret_cast<uint32_t *>(ws + p.off_itotal);
-  f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
-  f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
-  f.nbig = f.total_items + 2;
-  f.hugebins = reinterpret_cast<uint32_t *>(ws + p.off_huge);
-  f.nhuge = f.total_items + 3;
-  f.err = err;
-  uint32_t *sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
-  const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
+  const FinalArgs &f = L.f;
   GT_TIMED("k_bin_items", launch_bin_items(f, st));
-  GT_CHK(launch_fill(sstatus, (uint64_t)scan_tiles, 0u, st));
+  GT_CHK(launch_fill(L.sstatus, (uint64_t)L.scan_tiles, 0u, st));
   GT_CHK(launch_fill(f.total_items + 1, 3, 0u, st));  // scan ticket, big- and huge-bin counts
-  GT_TIMED("k_scan_u32", launch_scan_u32(f.nch, f.item_base, p.nbins, sstatus, f.total_items + 1, f.total_items, st));
+  GT_TIMED("k_scan_u32", launch_scan_u32(f.nch, f.item_base, f.nbins, L.sstatus, f.total_items + 1, f.total_items,
+                                         st));
   GT_TIMED("k_item_map", launch_item_map(f, st));
-  GT_TIMED("k_big_count", launch_big_count(f, p.max_items, st));
-  GT_TIMED("k_big_scan", launch_big_scan(f, p.max_big, p.max_huge, st));
-  GT_TIMED("k_final", launch_final(f, p.max_items, p.pay, st));
+  GT_TIMED("k_big_count", launch_big_count(f, L.max_items, st));
+  GT_TIMED("k_big_scan", launch_big_scan(f, L.max_big, L.max_huge, st));
+  GT_TIMED("k_final", launch_final(f, L.max_items, L.pay, st));
 #undef GT_TIMED
 #undef GT_CHK
   return GT_OK;
@@ -489,7 +543,34 @@ gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_
 
 }  // namespace gt
 
+// Persistent plans: every graph must fit the persistent kernel's bodies;
+// the pinned staging buffer, its event and the launch's grid.
+static gt_status persist_setup(gt_plan_st *plan) {
+  for (const GraphPlan &p : plan->graphs)
+    if (!persist_eligible(p)) return GT_ERR_UNSUPPORTED;
+  plan->pk_bytes = persist_tables_bytes(plan->count);
+  if (hipHostMalloc(&plan->pk_host, plan->pk_bytes, hipHostMallocDefault) != hipSuccess) {
+    plan->pk_host = nullptr;
+    return GT_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&plan->pk_event, hipEventDisableTiming) != hipSuccess) {
+    plan->pk_event = nullptr;
+    return GT_ERR_HIP;
+  }
+  int dev = 0, cus = 0;
+  const int per_cu = persistent_workgroups_per_cu();
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+      cus <= 0)
+    return GT_ERR_HIP;
+  plan->pk_grid = per_cu * cus;
+  return GT_OK;
+}
+
 gt_plan_st::~gt_plan_st() {
+  if (pk_event) (void)hipEventSynchronize(pk_event);  // no copy still reads the staging buffer
+  if (pk_event) (void)hipEventDestroy(pk_event);
+  if (pk_host) (void)hipHostFree(pk_host);
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : lane_events) (void)hipEventDestroy(e);
   if (fork_event) (void)hipEventDestroy(fork_event);
@@ -507,6 +588,7 @@ const char *gt_status_string(gt_status s) {
     case GT_ERR_UNSUPPORTED: return "unsupported parameters";
     case GT_ERR_HIP: return "HIP runtime error";
     case GT_ERR_COUNTER_OVERFLOW: return "counter overflow";
+    case GT_ERR_STALLED: return "persistent kernel stalled";
   }
   return "unknown status";
 }
@@ -518,7 +600,8 @@ gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes
   size_t total = 0;
   for (int32_t i = 0; i < count; ++i)
     total += align_up(graph_workspace_bound(graphs[i].n, graphs[i].m, graphs[i].payload != nullptr));
-  total += kAlign;  // status word
+  // status word, or a persistent plan's counters and tables
+  total += align_up(persist_counters_end(count)) + persist_tables_bytes(count);
   total += align_up(plan_scratch_bytes(graphs, count));
   *bytes_out = total;
   return GT_OK;
@@ -565,13 +648,14 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
                         (hipStream_t)stream);
     if (st != GT_OK) { delete plan; return st; }
   }
-  size_t base = kAlign;  // byte 0: device status word
-  for (int32_t i = 0; i < count; ++i) {
-    GraphPlan &p = plan->graphs[i];
-    finalize_params(p, base);
-    base = align_up(p.ws_end);
+  plan->persistent = (o.flags & GT_FLAG_PERSISTENT) != 0;
+  if (plan->persistent)
+    for (GraphPlan &p : plan->graphs) persist_coerce(p);
+  layout_plan(plan);
+  if (plan->persistent) {
+    st = persist_setup(plan);
+    if (st != GT_OK) { delete plan; return st; }
   }
-  plan->ws_bytes = std::max<size_t>(base, 256);
   *plan_out = plan;
   return GT_OK;
 }
@@ -638,6 +722,7 @@ gt_status gt_device_status(const void *workspace) {
   if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return GT_ERR_HIP;
   if (err & (kErrBadIndex | kErrBadOffsets)) return GT_ERR_INVALID_GRAPH;
   if (err & kErrOverflow) return GT_ERR_COUNTER_OVERFLOW;
+  if (err & kErrStall) return GT_ERR_STALLED;
   return GT_OK;
 }
 

@@ -91,6 +91,68 @@ struct FinalArgs {
   uint32_t *err;          // device status word
 };
 
+// Everything the kernels of one stable transposition need, derived from a
+// plan, the graph and the workspace (built on the host; the persistent
+// batched kernel reads it from device memory).
+struct StableLaunch {
+  const int64_t *O;
+  const int32_t *D;
+  int64_t n, m, ntiles, tile, nbins_total;
+  int passes, radix0, hist_blocks, variant;
+  bool pay, wide, validate;
+  HistArgs h;
+  uint32_t *err, *part, *tbsum, *toff, *sstatus;
+  uint16_t *tcnt;
+  uint64_t *digit, *bins, *dtot;
+  int32_t *tsrc;
+  uint32_t *status;  // look-back words of the passes after the first
+  uint64_t status_words;
+  uint32_t *ticket;
+  LsdArgs lsd[kMaxPasses];
+  bool pk[kMaxPasses];
+  FinalArgs f;
+  int64_t scan_tiles, max_items, max_big, max_huge;
+};
+
+// ---- The persistent batched kernel: one launch drains a device work queue
+// of (graph, phase, item) tickets for every graph of a batch, in dependency
+// order.  Phases of one stable transposition (variant-1 tiles, digits of at
+// most 9 bits, one or two passes, m < 2^31), each waiting for the previous
+// phase of its graph:
+enum PersistKind : uint32_t {
+  kPhFill, kPhValidate, kPhHist, kPhTileBsum, kPhTileBscan, kPhTileOff, kPhDigitReduce, kPhDigitScan, kPhTileSrc,
+  kPhPass0, kPhPass1, kPhBinItems, kPhScan, kPhItemMap, kPhBigCount, kPhBigScan, kPhHugeScan, kPhFinal
+};
+constexpr int kPersistMaxPhases = 18;  // phases of one graph, at most
+constexpr int kPersistFills = 4;
+struct PersistPhase {
+  uint32_t kind, graph, nitems;
+  uint32_t dep;    // index of the phase this one waits for, or kNoDep
+  uint64_t start;  // its first ticket (phases are stored in ticket order)
+  // kPhFill: word ranges to clear
+  uint32_t *fill[kPersistFills];
+  uint64_t fill_words[kPersistFills];
+};
+constexpr uint32_t kNoDep = 0xFFFFFFFFu;
+struct PersistArgs {
+  const StableLaunch *graphs;
+  const PersistPhase *phases;
+  int32_t nphases;
+  uint64_t total;              // tickets in the queue
+  unsigned long long *ticket;  // next ticket
+  uint32_t *done;              // [nphases] items finished and published
+  uint32_t *err;               // device status word
+};
+// A dependency wait that has not ended after this many sleeps sets this
+// status bit and gives up (the output is then undefined; no wait is endless).
+constexpr uint32_t kErrStall = 8u;
+// threads per workgroup of the persistent kernel, and its LDS
+constexpr int kPersistThreads = 512;
+size_t persistent_lds_bytes();
+// workgroups of the persistent kernel one CU holds at once (0 on error)
+int persistent_workgroups_per_cu();
+hipError_t launch_persistent(const PersistArgs &a, int grid, hipStream_t st);
+
 int64_t lsd_tile_size(int variant);
 // The tile variant that runs digits of up to max_bits bits (variants without
 // an instance for that width map to variant 1).

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/gt.h"
+#include "gt_internal.h"
 
 namespace gt {
 
@@ -91,6 +92,18 @@ struct gt_plan_st {
   std::vector<hipEvent_t> lane_events;
   hipEvent_t fork_event = nullptr;
   std::vector<int> lane_of;  // graph -> lane
+  // GT_FLAG_PERSISTENT: gt_transpose_batched drains one device work queue
+  // with the persistent kernel.  Workspace: byte 0 the status word, bytes
+  // 8..15 the queue's ticket, then one done counter per phase; after the
+  // graphs' regions, the graph descriptors and the phase table (copied from
+  // the pinned host staging buffer by every call).
+  bool persistent = false;
+  size_t off_pdesc = 0, off_pphase = 0;
+  void *pk_host = nullptr;  // hipHostMalloc'd: descriptors, then phases
+  size_t pk_bytes = 0;
+  hipEvent_t pk_event = nullptr;  // the last copy out of pk_host
+  bool pk_pending = false;
+  int pk_grid = 0;  // workgroups of the persistent launch
   ~gt_plan_st();
 };
 
@@ -103,10 +116,22 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
                         void *workspace, size_t workspace_bytes, hipStream_t st);
 gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
                         bool reset_status, Profiler *prof, hipStream_t st);
+StableLaunch stable_launch(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate);
 size_t unordered_workspace_end(GraphPlan &p, size_t base);
 gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
                             hipStream_t st);
 gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
                           hipStream_t st);
+// Persistent plans: the done counters start at this workspace byte; the
+// graph regions after the counters of kPersistMaxPhases phases per graph.
+constexpr size_t kPersistDoneOff = 16;
+size_t persist_counters_end(int32_t count);
+size_t persist_tables_bytes(int32_t count);
+// Variant-1 tiles, digits of at most 9 bits (the persistent kernel's bodies).
+void persist_coerce(GraphPlan &p);
+bool persist_eligible(const GraphPlan &p);
+// Offsets of every graph's region (and of a persistent plan's tables); sets
+// plan->ws_bytes.
+void layout_plan(gt_plan_st *plan);
 
 }  // namespace gt

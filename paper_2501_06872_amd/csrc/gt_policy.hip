@@ -212,8 +212,136 @@ static gt_status ensure_lanes(gt_plan_st *plan) {
   return GT_OK;
 }
 
+// ---- Persistent batched launch.  The phase table: every graph's phases in
+// pipeline order (PersistKind order), each waiting for the graph's previous
+// phase; the queue holds them level by level (all graphs' phases of one kind,
+// the largest graph first, before any phase of the next kind), so that the
+// items of a level find their graph's previous level finished or nearly so.
+static uint32_t clamp_items(int64_t x, int64_t hi) {
+  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(x, hi));
+}
+
+static int persist_phases(const GraphPlan &p, const StableLaunch &L, const gt_csc_t &out, int32_t g,
+                          bool validate, PersistPhase *ph) {
+  constexpr int64_t NT = kPersistThreads;
+  int k = 0;
+  auto add = [&](PersistKind kind, int64_t nitems) {
+    if (nitems <= 0) return;
+    PersistPhase &q = ph[k++];
+    q = PersistPhase{};
+    q.kind = kind;
+    q.graph = (uint32_t)g;
+    q.nitems = (uint32_t)nitems;
+  };
+  if (p.n == 0 || p.m == 0) {  // T = 0 everywhere
+    add(kPhFill, clamp_items((2 * (p.n + 1) + NT * 16 - 1) / (NT * 16), 64));
+    ph[k - 1].fill[0] = reinterpret_cast<uint32_t *>(out.offsets);
+    ph[k - 1].fill_words[0] = 2 * (uint64_t)(p.n + 1);
+    if (validate && p.n > 0) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
+    return k;
+  }
+  // counters and look-back words that start at zero
+  const uint64_t status_words = L.passes > 1 ? L.status_words : 0;
+  const uint64_t words = status_words + (uint64_t)L.scan_tiles + 3;
+  add(kPhFill, clamp_items((int64_t)((words + NT * 16 - 1) / (NT * 16)), 256));
+  ph[k - 1].fill[0] = L.status;
+  ph[k - 1].fill_words[0] = status_words;
+  ph[k - 1].fill[1] = L.sstatus;
+  ph[k - 1].fill_words[1] = (uint64_t)L.scan_tiles;
+  ph[k - 1].fill[2] = L.f.total_items + 1;  // scan ticket, big- and huge-bin counts
+  ph[k - 1].fill_words[2] = 3;
+  if (validate) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
+  const int64_t nblk = tile_scan_blocks(L.ntiles);
+  add(kPhHist, L.hist_blocks);
+  add(kPhTileBsum, nblk);
+  add(kPhTileBscan, L.radix0);
+  add(kPhTileOff, nblk);
+  if (L.passes > 1) add(kPhDigitReduce, (int64_t)L.passes * (kMaxRadix / 64));
+  add(kPhDigitScan, L.passes);
+  add(kPhTileSrc, (L.ntiles + NT - 1) / NT);
+  add(kPhPass0, L.ntiles);
+  if (L.passes > 1) add(kPhPass1, L.ntiles);
+  add(kPhBinItems, (L.f.nbins + NT - 1) / NT);
+  add(kPhScan, L.scan_tiles);
+  add(kPhItemMap, (L.f.nbins + NT - 1) / NT);
+  add(kPhBigCount, L.max_items);
+  add(kPhBigScan, L.max_big);
+  add(kPhHugeScan, L.max_huge);
+  add(kPhFinal, L.max_items);
+  return k;
+}
+
+static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
+                                    hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return GT_ERR_HIP;
+  // the previous call's copy may still read the staging buffer
+  if (plan->pk_pending && cap == hipStreamCaptureStatusNone) {
+    if (hipEventSynchronize(plan->pk_event) != hipSuccess) return GT_ERR_HIP;
+    plan->pk_pending = false;
+  }
+  const int32_t count = plan->count;
+  char *host = static_cast<char *>(plan->pk_host);
+  StableLaunch *desc = reinterpret_cast<StableLaunch *>(host);
+  PersistPhase *table = reinterpret_cast<PersistPhase *>(host + (plan->off_pphase - plan->off_pdesc));
+  // every graph's phases, then the queue order
+  std::vector<PersistPhase> all;
+  all.reserve((size_t)count * kPersistMaxPhases);
+  std::vector<int> first(count), nph(count);
+  PersistPhase buf[kPersistMaxPhases];
+  for (int32_t i = 0; i < count; ++i) {
+    const GraphPlan &p = plan->graphs[i];
+    desc[i] = stable_launch(p, graphs[i], outs[i], ws, plan->validate);
+    nph[i] = persist_phases(p, desc[i], outs[i], i, plan->validate, buf);
+    first[i] = (int)all.size();
+    all.insert(all.end(), buf, buf + nph[i]);
+  }
+  std::vector<int> order(all.size());
+  for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const PersistPhase &x = all[a], &y = all[b];
+    if (x.kind != y.kind) return x.kind < y.kind;
+    const int64_t mx = plan->graphs[x.graph].m, my = plan->graphs[y.graph].m;
+    if (mx != my) return mx > my;
+    return x.graph < y.graph;
+  });
+  std::vector<uint32_t> pos(all.size());
+  for (size_t j = 0; j < order.size(); ++j) pos[order[j]] = (uint32_t)j;
+  uint64_t total = 0;
+  for (size_t j = 0; j < order.size(); ++j) {
+    const int a = order[j];
+    PersistPhase q = all[a];
+    const int i = (int)q.graph;
+    q.dep = a > first[i] ? pos[a - 1] : kNoDep;  // the graph's previous phase
+    q.start = total;
+    total += q.nitems;
+    table[j] = q;
+  }
+  const int32_t nphases = (int32_t)order.size();
+  const size_t copy = (plan->off_pphase - plan->off_pdesc) + sizeof(PersistPhase) * (size_t)nphases;
+  if (hipMemcpyAsync(ws + plan->off_pdesc, host, copy, hipMemcpyHostToDevice, st) != hipSuccess) return GT_ERR_HIP;
+  if (hipEventRecord(plan->pk_event, st) != hipSuccess) return GT_ERR_HIP;
+  plan->pk_pending = true;
+  // status word, ticket and done counters
+  if (launch_fill(reinterpret_cast<uint32_t *>(ws), (kPersistDoneOff + 4 * (size_t)nphases) / 4, 0u, st) !=
+      hipSuccess)
+    return GT_ERR_HIP;
+  PersistArgs a{};
+  a.graphs = reinterpret_cast<const StableLaunch *>(ws + plan->off_pdesc);
+  a.phases = reinterpret_cast<const PersistPhase *>(ws + plan->off_pphase);
+  a.nphases = nphases;
+  a.total = total;
+  a.ticket = reinterpret_cast<unsigned long long *>(ws + 8);
+  a.done = reinterpret_cast<uint32_t *>(ws + kPersistDoneOff);
+  a.err = reinterpret_cast<uint32_t *>(ws);
+  const int grid = (int)std::min<uint64_t>((uint64_t)plan->pk_grid, total);
+  if (launch_persistent(a, grid, st) != hipSuccess) return GT_ERR_HIP;
+  return GT_OK;
+}
+
 gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
                           hipStream_t st) {
+  if (plan->persistent) return enqueue_persistent(plan, graphs, outs, ws, st);
   gt_status s = ensure_lanes(plan);
   if (s != GT_OK) return s;
   if (launch_fill(reinterpret_cast<uint32_t *>(ws), 1, 0u, st) != hipSuccess) return GT_ERR_HIP;
@@ -304,14 +432,16 @@ gt_status gt_autotune(const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t 
 gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config) {
   if (plan == nullptr || i < 0 || i >= plan->count || config < 0 || config >= kMlpOut) return GT_ERR_INVALID_ARGUMENT;
   GraphPlan &p = plan->graphs[i];
+  const GraphPlan keep = p;
   config_params(config, &p.fine_bits, &p.digit_bits, &p.variant);
   p.config = config;
-  size_t base = 256;
-  for (int32_t k = 0; k < plan->count; ++k) {
-    finalize_params(plan->graphs[k], base);
-    base = align256(plan->graphs[k].ws_end);
+  if (plan->persistent) persist_coerce(p);
+  layout_plan(plan);
+  if (plan->persistent && !persist_eligible(p)) {
+    p = keep;
+    layout_plan(plan);
+    return GT_ERR_UNSUPPORTED;
   }
-  plan->ws_bytes = base;
   return GT_OK;
 }
 

@@ -1,0 +1,143 @@
+"""GPU: the persistent batched kernel (GT_FLAG_PERSISTENT), one launch that
+drains a device work queue of every graph's phases, against the oracle:
+eager, with payloads, empty and single-pass graphs, offsets validation, the
+learned policy, back-to-back calls, and replays of a captured HIP graph.
+Every case prints its name first."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def batch(count=24, seed=41, shift=6):
+    """Uneven batch (sizes 2^10 .. 2^16 after the shift), plus an empty
+    graph, a graph without edges, a one-vertex graph with self loops, a small
+    graph that needs a single partition pass and two that need two."""
+    specs = gen.batch_specs(count, seed=seed)
+    for s in specs:
+        s["n"] = max(1024, s["n"] >> shift)
+    host = [gen.from_spec(s) for s in specs]
+    host.append((np.zeros(1, np.int64), np.zeros(0, np.int32), None))                 # n = 0
+    host.append((np.zeros(6, np.int64), np.zeros(0, np.int32), None))                 # n = 5, m = 0
+    host.append((np.array([0, 3], np.int64), np.zeros(3, np.int32),
+                 np.array([7, 8, 9], np.uint32)))                                     # n = 1, m = 3
+    host.append(gen.generate(gen.FAM_UNIFORM, 700, 6, seed=3, payload=True))  # one pass
+    # two partition passes (2^20 vertices, average degree 4)
+    host.append(gen.generate(gen.FAM_RMAT, 1 << 20, 4, seed=5, permute=True, payload=True))
+    host.append(gen.generate(gen.FAM_GEOMETRIC, 1 << 20, 4, seed=6))
+    return host
+
+
+def to_dev(O, D, P, dev):
+    return (torch.from_numpy(O).to(dev), torch.from_numpy(D).to(dev),
+            torch.from_numpy(P.view(np.int32)).to(dev) if P is not None else None)
+
+
+def check(outs, host):
+    for i, ((T, S, Q), (O, D, P)) in enumerate(zip(outs, host)):
+        rT, rS, rQ = oracle.transpose(O, D, P)
+        assert np.array_equal(T.cpu().numpy(), rT), f"graph {i}: offsets"
+        assert np.array_equal(S.cpu().numpy(), rS), f"graph {i}: sources"
+        if P is not None:
+            assert np.array_equal(Q.cpu().numpy().view(np.uint32), rQ), f"graph {i}: payload"
+
+
+def persistent_plan(gt, dev, **kw):
+    flags = kw.pop("flags", 0) | gt.FLAG_PERSISTENT
+    plan = gt.Plan(dev, gt.make_options(flags=flags, **kw))
+    for i in range(len(dev)):
+        p = plan.params(i)
+        if dev[i][1].numel() > 0 and dev[i][0].numel() > 1:
+            assert p["variant"] == 1 and p["digit_bits"] <= 9 and p["passes"] <= 2, (i, p)
+    return plan
+
+
+@pytest.mark.parametrize("validate", [False, True])
+def test_persistent_eager_matches_oracle(hip_device, validate):
+    import paper_2501_06872_amd as gt
+    host = batch()
+    say(f"[case] persistent batched eager, {len(host)} graphs, validate={validate}")
+    dev = [to_dev(*g, hip_device) for g in host]
+    plan = persistent_plan(gt, dev, validate=validate)
+    assert any(plan.params(i)["passes"] == 1 for i in range(len(dev)) if dev[i][1].numel() > 0)
+    assert any(plan.params(i)["passes"] == 2 for i in range(len(dev)))
+    outs = plan.run_batched(dev)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    check(outs, host)
+
+
+def test_persistent_back_to_back(hip_device):
+    """Two calls without a synchronisation between them, into different
+    outputs: the second waits for the first call's copy of its tables."""
+    import paper_2501_06872_amd as gt
+    host = batch(12, seed=43)
+    say(f"[case] persistent batched, two calls back to back, {len(host)} graphs")
+    dev = [to_dev(*g, hip_device) for g in host]
+    plan = persistent_plan(gt, dev)
+    a = plan.run_batched(dev)
+    b = plan.run_batched(dev)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    check(a, host)
+    check(b, host)
+
+
+def test_persistent_mlp_policy(hip_device):
+    import paper_2501_06872_amd as gt
+    from paper_2501_06872_amd import mlp_model
+    host = batch(16, seed=47, shift=4)
+    say(f"[case] persistent batched, learned policy, {len(host)} graphs")
+    dev = [to_dev(*g, hip_device) for g in host]
+    plan = persistent_plan(gt, dev, policy=gt.POLICY_MLP, model_path=mlp_model.DEFAULT_PATH)
+    outs = plan.run_batched(dev)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    check(outs, host)
+
+
+def test_persistent_graph_replay(hip_device):
+    import paper_2501_06872_amd as gt
+    host = batch(16, seed=45)
+    say(f"[case] persistent batched, hipGraph replay, {len(host)} graphs")
+    dev = [to_dev(*g, hip_device) for g in host]
+    plan = persistent_plan(gt, dev)
+    outs = [plan.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(dev)]
+    plan.run_batched(dev, outs)
+    torch.cuda.synchronize()
+    check(outs, host)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run_batched(dev, outs)
+    for rep in range(3):
+        for T, S, Q in outs:  # scribble over the outputs between replays
+            T.fill_(-7)
+            S.fill_(-7)
+            if Q is not None:
+                Q.fill_(7)
+        junk = torch.randn(1 << 20, device=hip_device).sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        assert plan.device_status() == 0
+        check(outs, host)
+        del junk
+
+
+def test_persistent_refuses_wide_status(hip_device):
+    import paper_2501_06872_amd as gt
+    host = batch(2, seed=49)
+    say("[case] persistent plan with 64-bit look-back words is refused")
+    dev = [to_dev(*g, hip_device) for g in host]
+    with pytest.raises(gt.GTError) as e:
+        gt.Plan(dev, gt.make_options(flags=gt.FLAG_PERSISTENT | gt.FLAG_WIDE_STATUS))
+    assert e.value.status == gt.GT_ERR_UNSUPPORTED
