@@ -219,9 +219,14 @@ size_t persist_counters_end(int32_t count) {
   return kPersistDoneOff + 4 * (size_t)count * kPersistMaxPhases;
 }
 
-size_t persist_tables_bytes(int32_t count) {
+size_t persist_tables_bytes(int32_t count, uint64_t tab_entries) {
   return align_up(sizeof(StableLaunch) * (size_t)count) +
-         align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases);
+         align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases) + align_up(4 * (size_t)tab_entries);
+}
+
+uint64_t persist_item_bound(int64_t n, int64_t m) {
+  // fixed-size phases, tiles of the passes and their scans, bins, work items
+  return 8192 + 8 * ((uint64_t)m / 4096 + 1) + 4 * ((uint64_t)n + 1);
 }
 
 void persist_coerce(GraphPlan &p) {
@@ -242,9 +247,17 @@ void layout_plan(gt_plan_st *plan) {
     base = align_up(p.ws_end);
   }
   if (plan->persistent) {
+    uint64_t items = 0;
+    PersistPhase buf[kPersistMaxPhases];
+    for (const GraphPlan &p : plan->graphs) {
+      const int k = persist_phases(p, nullptr, nullptr, 0, plan->validate, buf);
+      for (int j = 0; j < k; ++j) items += buf[j].nitems;
+    }
+    plan->ptab_entries = (items >> kPersistTabShift) + 2;  // tickets <= items
     plan->off_pdesc = base;
     plan->off_pphase = base + align_up(sizeof(StableLaunch) * (size_t)plan->count);
-    base += persist_tables_bytes(plan->count);
+    plan->off_ptab = plan->off_pphase + align_up(sizeof(PersistPhase) * (size_t)plan->count * kPersistMaxPhases);
+    base += persist_tables_bytes(plan->count, plan->ptab_entries);
   }
   plan->ws_bytes = std::max<size_t>(base, 256);
 }
@@ -545,14 +558,29 @@ gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_
 
 // Persistent plans: every graph must fit the persistent kernel's bodies;
 // the pinned staging buffer, its event and the launch's grid.
-static gt_status persist_setup(gt_plan_st *plan) {
-  for (const GraphPlan &p : plan->graphs)
-    if (!persist_eligible(p)) return GT_ERR_UNSUPPORTED;
-  plan->pk_bytes = persist_tables_bytes(plan->count);
-  if (hipHostMalloc(&plan->pk_host, plan->pk_bytes, hipHostMallocDefault) != hipSuccess) {
+gt_status gt::persist_staging(gt_plan_st *plan) {
+  const size_t need = persist_tables_bytes(plan->count, plan->ptab_entries);
+  if (plan->pk_host != nullptr && plan->pk_bytes >= need) return GT_OK;
+  if (plan->pk_host != nullptr) {
+    if (plan->pk_event != nullptr && hipEventSynchronize(plan->pk_event) != hipSuccess) return GT_ERR_HIP;
+    (void)hipHostFree(plan->pk_host);
+    plan->pk_host = nullptr;
+    plan->pk_bytes = 0;
+    plan->pk_pending = false;
+  }
+  if (hipHostMalloc(&plan->pk_host, need, hipHostMallocDefault) != hipSuccess) {
     plan->pk_host = nullptr;
     return GT_ERR_HIP;
   }
+  plan->pk_bytes = need;
+  return GT_OK;
+}
+
+static gt_status persist_setup(gt_plan_st *plan) {
+  for (const GraphPlan &p : plan->graphs)
+    if (!persist_eligible(p)) return GT_ERR_UNSUPPORTED;
+  const gt_status s = persist_staging(plan);
+  if (s != GT_OK) return s;
   if (hipEventCreateWithFlags(&plan->pk_event, hipEventDisableTiming) != hipSuccess) {
     plan->pk_event = nullptr;
     return GT_ERR_HIP;
@@ -601,7 +629,9 @@ gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes
   for (int32_t i = 0; i < count; ++i)
     total += align_up(graph_workspace_bound(graphs[i].n, graphs[i].m, graphs[i].payload != nullptr));
   // status word, or a persistent plan's counters and tables
-  total += align_up(persist_counters_end(count)) + persist_tables_bytes(count);
+  uint64_t items = 0;
+  for (int32_t i = 0; i < count; ++i) items += persist_item_bound(graphs[i].n, graphs[i].m);
+  total += align_up(persist_counters_end(count)) + persist_tables_bytes(count, (items >> kPersistTabShift) + 2);
   total += align_up(plan_scratch_bytes(graphs, count));
   *bytes_out = total;
   return GT_OK;

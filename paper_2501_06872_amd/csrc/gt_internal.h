@@ -128,6 +128,7 @@ constexpr int kPersistFills = 4;
 struct PersistPhase {
   uint32_t kind, graph, nitems;
   uint32_t dep;    // index of the phase this one waits for, or kNoDep
+  uint32_t chunk;  // items per ticket (consecutive items, run in order)
   uint64_t start;  // its first ticket (phases are stored in ticket order)
   // kPhFill: word ranges to clear
   uint32_t *fill[kPersistFills];
@@ -139,10 +140,13 @@ struct PersistArgs {
   const PersistPhase *phases;
   int32_t nphases;
   uint64_t total;              // tickets in the queue
+  // tab[i]: the phase holding ticket i << kPersistTabShift (i <= total >> shift)
+  const uint32_t *tab;
   unsigned long long *ticket;  // next ticket
   uint32_t *done;              // [nphases] items finished and published
   uint32_t *err;               // device status word
 };
+constexpr int kPersistTabShift = 4;
 // A dependency wait that has not ended after this many sleeps sets this
 // status bit and gives up (the output is then undefined; no wait is endless).
 constexpr uint32_t kErrStall = 8u;

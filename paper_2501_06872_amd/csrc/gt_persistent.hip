@@ -22,23 +22,26 @@ namespace gt {
 using namespace pb;
 
 // ---------------------------------------------------------------------------
-// Persistent batched kernel.  Every workgroup loops: take the next ticket of
-// the queue, find its phase (phases are stored in ticket order), wait until
-// the phase it depends on (the previous phase of its graph) has published
-// all its items, run the item with the shared bodies, count it.  Tickets are
-// taken in queue order, so every item a running item waits for -- a whole
-// earlier phase, or an earlier tile of its own look-back chain -- was taken
-// before it by a workgroup that is running, and a workgroup publishes what it
-// holds before it can wait on anything outside its current phase: the queue
-// always drains.  A workgroup publishes its finished items of a phase (its
-// stores complete, a device-scope release, then one atomic add) when it moves
-// to another phase, every kPublishEvery items, and when the queue is empty.
+// Persistent batched kernel.  Every workgroup loops: take a ticket of the
+// queue, find its phase (phases are stored in ticket order; a coarse table
+// brackets the search), wait until the phase it depends on (the previous
+// phase of its graph) has published all its items, run the ticket's items
+// (one, or a run of up to four consecutive items of a long phase) with the
+// shared bodies, count them.  Outside the look-back phases a workgroup takes
+// its next ticket while it runs the current one.  Tickets are taken in queue
+// order, so every item a running item waits for -- a whole earlier phase, or
+// an earlier tile of its own look-back chain -- belongs to a smaller ticket,
+// held by a running workgroup that runs it no later than after its current
+// ticket; and a workgroup publishes what it holds before it can wait on
+// anything outside its current phase: the queue always drains.  A workgroup
+// publishes its finished items of a phase (its stores complete, a
+// device-scope release, then one atomic add) when it moves to another phase
+// and when the queue is empty.
 // The L2 of an XCD is not coherent with the others': the release writes this
 // XCD's dirty lines back, and the first item a workgroup runs after a phase it
 // depends on has completed starts with a device-scope acquire (which drops the
 // clean lines of this XCD's L2 and of the CU's L1).
 // ---------------------------------------------------------------------------
-constexpr int kPublishEvery = 16;
 constexpr uint32_t kSpinLimit = 1u << 26;  // sleeps (~50 ns each) before a wait gives up
 
 union PersistShared {
@@ -181,6 +184,19 @@ __device__ __forceinline__ void persist_publish(const PersistArgs &pa, int32_t p
   atomicAdd(&pa.done[phase], count);
 }
 
+// The phase holding ticket t: the coarse table brackets it, a binary search
+// inside the bracket (usually empty) finds it.
+__device__ __forceinline__ int32_t persist_phase_of(const PersistArgs &pa, unsigned long long t) {
+  const uint64_t b = t >> kPersistTabShift;
+  int32_t lo = (int32_t)pa.tab[b], hi = (int32_t)pa.tab[b + 1] + 1;
+  if (hi > pa.nphases) hi = pa.nphases;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (pa.phases[mid].start <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // 2 workgroups of 8 waves per CU: the bodies fit 128 VGPRs without spilling
 __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_persistent(
     PersistArgs pa) {
@@ -189,23 +205,20 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
   __shared__ unsigned long long s_ticket;
   __shared__ int32_t s_phase;
   const int tid = threadIdx.x;
-  // thread 0: finished items not yet published, and the last phase whose
-  // completion this workgroup has acquired
+  // thread 0: the next ticket (taken while the current one runs), finished
+  // items not yet published, and the last phase whose completion this
+  // workgroup has acquired
+  unsigned long long next = 0;
+  bool have_next = false;
   int32_t held_phase = -1;
   uint32_t held = 0;
   uint32_t acquired = kNoDep;
   while (true) {
     if (tid == 0) {
-      const unsigned long long t = atomicAdd(pa.ticket, 1ull);
-      s_ticket = t;
-      if (t < pa.total) {  // the last phase whose start is <= t
-        int32_t lo = 0, hi = pa.nphases;
-        while (hi - lo > 1) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (pa.phases[mid].start <= t) lo = mid; else hi = mid;
-        }
-        s_phase = lo;
-      }
+      if (!have_next) next = atomicAdd(pa.ticket, 1ull);
+      have_next = false;
+      s_ticket = next;
+      if (next < pa.total) s_phase = persist_phase_of(pa, next);
     }
     __syncthreads();
     // uniform across the workgroup: read into scalar registers, so that the
@@ -232,19 +245,28 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
         __threadfence();  // acquire: the phase's writes before this item's reads
         acquired = P.dep;
       }
+      // the next ticket, taken now: its latency hides behind this one's
+      // items.  Not in a look-back phase: a tile whose ticket waits behind
+      // another tile holds up every later tile of the phase.
+      if (P.kind != kPhPass1 && P.kind != kPhScan) {
+        next = atomicAdd(pa.ticket, 1ull);
+        have_next = true;
+      }
     }
     __syncthreads();
-    persist_item(P, pa.graphs + P.graph, (int64_t)(t - P.start), sh);
-    // every thread's stores of the item complete, then no thread uses the
-    // item's LDS any more
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    const uint32_t chunk = P.chunk, nitems = P.nitems;
+    const uint64_t first = (t - P.start) * chunk;
+    const uint32_t count = (uint32_t)(first + chunk <= nitems ? chunk : nitems - first);
+    for (uint32_t c = 0; c < count; ++c) {
+      persist_item(P, pa.graphs + P.graph, (int64_t)(first + c), sh);
+      // every thread's stores of the item complete, then no thread uses the
+      // item's LDS any more
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
     if (tid == 0) {
       held_phase = ph;
-      if (++held >= (uint32_t)kPublishEvery) {
-        persist_publish(pa, ph, held);
-        held = 0;
-      }
+      held += count;
     }
   }
   if (tid == 0 && held != 0) persist_publish(pa, held_phase, held);

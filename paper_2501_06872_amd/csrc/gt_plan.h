@@ -98,7 +98,8 @@ struct gt_plan_st {
   // graphs' regions, the graph descriptors and the phase table (copied from
   // the pinned host staging buffer by every call).
   bool persistent = false;
-  size_t off_pdesc = 0, off_pphase = 0;
+  size_t off_pdesc = 0, off_pphase = 0, off_ptab = 0;
+  uint64_t ptab_entries = 0;  // capacity of the ticket -> phase table
   void *pk_host = nullptr;  // hipHostMalloc'd: descriptors, then phases
   size_t pk_bytes = 0;
   hipEvent_t pk_event = nullptr;  // the last copy out of pk_host
@@ -126,7 +127,14 @@ gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc
 // graph regions after the counters of kPersistMaxPhases phases per graph.
 constexpr size_t kPersistDoneOff = 16;
 size_t persist_counters_end(int32_t count);
-size_t persist_tables_bytes(int32_t count);
+size_t persist_tables_bytes(int32_t count, uint64_t tab_entries);
+// Items of all phases of a graph of n vertices and m edges, at most, for any
+// parameters (sizes the ticket -> phase table before a plan exists).
+uint64_t persist_item_bound(int64_t n, int64_t m);
+// (Re)allocate a persistent plan's pinned staging buffer for its tables.
+gt_status persist_staging(gt_plan_st *plan);
+int persist_phases(const GraphPlan &p, const StableLaunch *L, const gt_csc_t *out, int32_t g, bool validate,
+                   PersistPhase *ph);
 // Variant-1 tiles, digits of at most 9 bits (the persistent kernel's bodies).
 void persist_coerce(GraphPlan &p);
 bool persist_eligible(const GraphPlan &p);

@@ -221,8 +221,10 @@ static uint32_t clamp_items(int64_t x, int64_t hi) {
   return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(x, hi));
 }
 
-static int persist_phases(const GraphPlan &p, const StableLaunch &L, const gt_csc_t &out, int32_t g,
-                          bool validate, PersistPhase *ph) {
+// The phases of one graph (at most kPersistMaxPhases), item counts from the
+// plan alone; with a descriptor L, also the ranges the first phase clears.
+int persist_phases(const GraphPlan &p, const StableLaunch *L, const gt_csc_t *out, int32_t g, bool validate,
+                   PersistPhase *ph) {
   constexpr int64_t NT = kPersistThreads;
   int k = 0;
   auto add = [&](PersistKind kind, int64_t nitems) {
@@ -232,43 +234,58 @@ static int persist_phases(const GraphPlan &p, const StableLaunch &L, const gt_cs
     q.kind = kind;
     q.graph = (uint32_t)g;
     q.nitems = (uint32_t)nitems;
+    q.chunk = 1;
   };
   if (p.n == 0 || p.m == 0) {  // T = 0 everywhere
     add(kPhFill, clamp_items((2 * (p.n + 1) + NT * 16 - 1) / (NT * 16), 64));
-    ph[k - 1].fill[0] = reinterpret_cast<uint32_t *>(out.offsets);
-    ph[k - 1].fill_words[0] = 2 * (uint64_t)(p.n + 1);
+    if (out) {
+      ph[k - 1].fill[0] = reinterpret_cast<uint32_t *>(out->offsets);
+      ph[k - 1].fill_words[0] = 2 * (uint64_t)(p.n + 1);
+    }
     if (validate && p.n > 0) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
     return k;
   }
+  const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
+  const int64_t status_words = p.passes > 1 ? p.ntiles * ((int64_t)1 << p.max_bits) : 0;
   // counters and look-back words that start at zero
-  const uint64_t status_words = L.passes > 1 ? L.status_words : 0;
-  const uint64_t words = status_words + (uint64_t)L.scan_tiles + 3;
-  add(kPhFill, clamp_items((int64_t)((words + NT * 16 - 1) / (NT * 16)), 256));
-  ph[k - 1].fill[0] = L.status;
-  ph[k - 1].fill_words[0] = status_words;
-  ph[k - 1].fill[1] = L.sstatus;
-  ph[k - 1].fill_words[1] = (uint64_t)L.scan_tiles;
-  ph[k - 1].fill[2] = L.f.total_items + 1;  // scan ticket, big- and huge-bin counts
-  ph[k - 1].fill_words[2] = 3;
+  add(kPhFill, clamp_items((status_words + scan_tiles + 3 + NT * 16 - 1) / (NT * 16), 256));
+  if (L) {
+    ph[k - 1].fill[0] = L->status;
+    ph[k - 1].fill_words[0] = (uint64_t)status_words;
+    ph[k - 1].fill[1] = L->sstatus;
+    ph[k - 1].fill_words[1] = (uint64_t)scan_tiles;
+    ph[k - 1].fill[2] = L->f.total_items + 1;  // scan ticket, big- and huge-bin counts
+    ph[k - 1].fill_words[2] = 3;
+  }
   if (validate) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
-  const int64_t nblk = tile_scan_blocks(L.ntiles);
-  add(kPhHist, L.hist_blocks);
+  const int64_t nblk = tile_scan_blocks(p.ntiles);
+  add(kPhHist, std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles)));
   add(kPhTileBsum, nblk);
-  add(kPhTileBscan, L.radix0);
+  add(kPhTileBscan, (int64_t)1 << p.bits[0]);
   add(kPhTileOff, nblk);
-  if (L.passes > 1) add(kPhDigitReduce, (int64_t)L.passes * (kMaxRadix / 64));
-  add(kPhDigitScan, L.passes);
-  add(kPhTileSrc, (L.ntiles + NT - 1) / NT);
-  add(kPhPass0, L.ntiles);
-  if (L.passes > 1) add(kPhPass1, L.ntiles);
-  add(kPhBinItems, (L.f.nbins + NT - 1) / NT);
-  add(kPhScan, L.scan_tiles);
-  add(kPhItemMap, (L.f.nbins + NT - 1) / NT);
-  add(kPhBigCount, L.max_items);
-  add(kPhBigScan, L.max_big);
-  add(kPhHugeScan, L.max_huge);
-  add(kPhFinal, L.max_items);
+  if (p.passes > 1) add(kPhDigitReduce, (int64_t)p.passes * (kMaxRadix / 64));
+  add(kPhDigitScan, p.passes);
+  add(kPhTileSrc, (p.ntiles + NT - 1) / NT);
+  add(kPhPass0, p.ntiles);
+  if (p.passes > 1) add(kPhPass1, p.ntiles);
+  add(kPhBinItems, (p.nbins + NT - 1) / NT);
+  add(kPhScan, scan_tiles);
+  add(kPhItemMap, (p.nbins + NT - 1) / NT);
+  add(kPhBigCount, p.max_items);
+  add(kPhBigScan, p.max_big);
+  add(kPhHugeScan, p.max_huge);
+  add(kPhFinal, p.max_items);
   return k;
+}
+
+// Items per ticket: long phases hand out runs of up to 4 consecutive items
+// (fewer tickets and dependency checks), as long as every resident
+// workgroup still gets several tickets of the phase.  Look-back phases take
+// one item per ticket: a run's last tile would hold up the next run's first.
+static uint32_t persist_chunk(uint32_t kind, uint32_t nitems, int grid) {
+  if (kind == kPhPass1 || kind == kPhScan) return 1;
+  const int64_t c = (int64_t)nitems / (8 * (int64_t)std::max(grid, 1));
+  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(c, 4));
 }
 
 static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
@@ -284,17 +301,18 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
   char *host = static_cast<char *>(plan->pk_host);
   StableLaunch *desc = reinterpret_cast<StableLaunch *>(host);
   PersistPhase *table = reinterpret_cast<PersistPhase *>(host + (plan->off_pphase - plan->off_pdesc));
+  uint32_t *tab = reinterpret_cast<uint32_t *>(host + (plan->off_ptab - plan->off_pdesc));
   // every graph's phases, then the queue order
   std::vector<PersistPhase> all;
   all.reserve((size_t)count * kPersistMaxPhases);
-  std::vector<int> first(count), nph(count);
+  std::vector<int> first(count);
   PersistPhase buf[kPersistMaxPhases];
   for (int32_t i = 0; i < count; ++i) {
     const GraphPlan &p = plan->graphs[i];
     desc[i] = stable_launch(p, graphs[i], outs[i], ws, plan->validate);
-    nph[i] = persist_phases(p, desc[i], outs[i], i, plan->validate, buf);
+    const int k = persist_phases(p, &desc[i], &outs[i], i, plan->validate, buf);
     first[i] = (int)all.size();
-    all.insert(all.end(), buf, buf + nph[i]);
+    all.insert(all.end(), buf, buf + k);
   }
   std::vector<int> order(all.size());
   for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
@@ -313,12 +331,22 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
     PersistPhase q = all[a];
     const int i = (int)q.graph;
     q.dep = a > first[i] ? pos[a - 1] : kNoDep;  // the graph's previous phase
+    q.chunk = persist_chunk(q.kind, q.nitems, plan->pk_grid);
     q.start = total;
-    total += q.nitems;
+    total += (q.nitems + q.chunk - 1) / q.chunk;
     table[j] = q;
   }
   const int32_t nphases = (int32_t)order.size();
-  const size_t copy = (plan->off_pphase - plan->off_pdesc) + sizeof(PersistPhase) * (size_t)nphases;
+  if (total == 0) return GT_OK;
+  // coarse ticket -> phase table
+  const uint64_t ntab = (total >> kPersistTabShift) + 2;
+  if (ntab > plan->ptab_entries) return GT_ERR_INVALID_ARGUMENT;
+  for (uint64_t b = 0, j = 0; b < ntab; ++b) {
+    const uint64_t t = std::min<uint64_t>(b << kPersistTabShift, total - 1);
+    while (j + 1 < (uint64_t)nphases && table[j + 1].start <= t) ++j;
+    tab[b] = (uint32_t)j;
+  }
+  const size_t copy = (plan->off_ptab - plan->off_pdesc) + sizeof(uint32_t) * (size_t)ntab;
   if (hipMemcpyAsync(ws + plan->off_pdesc, host, copy, hipMemcpyHostToDevice, st) != hipSuccess) return GT_ERR_HIP;
   if (hipEventRecord(plan->pk_event, st) != hipSuccess) return GT_ERR_HIP;
   plan->pk_pending = true;
@@ -331,6 +359,7 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
   a.phases = reinterpret_cast<const PersistPhase *>(ws + plan->off_pphase);
   a.nphases = nphases;
   a.total = total;
+  a.tab = reinterpret_cast<const uint32_t *>(ws + plan->off_ptab);
   a.ticket = reinterpret_cast<unsigned long long *>(ws + 8);
   a.done = reinterpret_cast<uint32_t *>(ws + kPersistDoneOff);
   a.err = reinterpret_cast<uint32_t *>(ws);
@@ -442,7 +471,7 @@ gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config) {
     layout_plan(plan);
     return GT_ERR_UNSUPPORTED;
   }
-  return GT_OK;
+  return plan->persistent ? persist_staging(plan) : GT_OK;
 }
 
 }  // extern "C"
