@@ -69,8 +69,8 @@ def kernel_bytes(name, n, m, w, passes, packed=False):
     return 0
 
 
-KERNEL_SOURCES = ("paper_2501_06872_amd/csrc/gt_kernels.hip", "paper_2501_06872_amd/csrc/gt_device.hpp",
-                  "paper_2501_06872_amd/csrc/gt_internal.h")
+KERNEL_SOURCES = ("paper_2501_06872_amd/csrc/gt_kernels.hip", "paper_2501_06872_amd/csrc/gt_bodies.hpp",
+                  "paper_2501_06872_amd/csrc/gt_device.hpp", "paper_2501_06872_amd/csrc/gt_internal.h")
 
 
 def measured_traffic(workload, kernel):

@@ -45,7 +45,7 @@ KERNELS = ("k_hist", "k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2", "k_big_count",
 
 def command(workload, tag):
     return (f"rocprofv3 --pmc {' '.join(PASSES[tag])} -d <dir> -o {tag} -- "
-            f"python3 bench.py --workload {workload} --steps 2 --warmup 1 --no-cpu-baseline")
+            f"python3 bench.py --workload {workload} --steps 2 --warmup 1 --no-cpu-baseline --no-batch")
 
 
 def summarise(workload, passes, d, edges):

@@ -1,6 +1,7 @@
 """Summarise rocprofv3 runs of bench.py into profiles/gt_kernels_<workload>.txt.
 
     python -m paper_2501_06872_amd.profile_summary <workload> <passes> <dir>
+    python -m paper_2501_06872_amd.profile_summary batch512 --batch <dir>
 
 <dir> holds the three rocprofv3 databases of one workload, named as the
 commands printed in the summary make them (trace_results.db,
@@ -19,8 +20,8 @@ import sqlite3
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ("paper_2501_06872_amd/csrc/gt_kernels.hip", "paper_2501_06872_amd/csrc/gt_device.hpp",
-                  "paper_2501_06872_amd/csrc/gt_internal.h")
+KERNEL_SOURCES = ("paper_2501_06872_amd/csrc/gt_kernels.hip", "paper_2501_06872_amd/csrc/gt_bodies.hpp",
+                  "paper_2501_06872_amd/csrc/gt_device.hpp", "paper_2501_06872_amd/csrc/gt_internal.h")
 
 
 def label(name, passes):
@@ -70,7 +71,7 @@ def summarise(workload, passes, d):
     for s in KERNEL_SOURCES:
         with open(os.path.join(ROOT, s), "rb") as f:
             h.update(f.read())
-    cmd = f"python3 bench.py --workload {workload} --steps 5 --warmup 2 --no-cpu-baseline --calibrate"
+    cmd = f"python3 bench.py --workload {workload} --steps 5 --warmup 2 --no-cpu-baseline --no-batch --calibrate"
     out = [f"# Kernels of the transposition path, workload {workload} (MI355X, one GPU)", "",
            "Commands (from the repository root; cd /tmp && export TMPDIR=/tmp first):",
            f"  rocprofv3 --kernel-trace --stats -d <dir> -o trace -- {cmd}",
@@ -108,8 +109,47 @@ def summarise(workload, passes, d):
     return "\n".join(out) + "\n"
 
 
+def summarise_batch(d):
+    """Kernel trace of bench.py --workload batch512: calls and durations per
+    kernel over the whole run (plain per-graph launches, the batched plans
+    over internal streams, the persistent kernel), and the persistent
+    kernel's launches one by one (each transposes the whole batch)."""
+    con = sqlite3.connect(os.path.join(d, "trace_results.db"))
+    tr = con.execute("select name, duration from kernels").fetchall()
+    stats = collections.OrderedDict()
+    pers = []
+    for n, dur in tr:
+        k = label(n, 2)
+        s = stats.setdefault(k, [0, 0.0])
+        s[0] += 1
+        s[1] += dur
+        if k == "k_persistent":
+            pers.append(dur / 1e6)
+    cmd = "python3 bench.py --workload batch512 --steps 2 --warmup 1 --no-autotune"
+    out = ["# Kernels of the 512-graph batch (MI355X, one GPU)", "",
+           "Commands (from the repository root; cd /tmp && export TMPDIR=/tmp first):",
+           f"  rocprofv3 --kernel-trace --stats -d <dir> -o trace -- {cmd}",
+           "  python -m paper_2501_06872_amd.profile_summary batch512 --batch <dir>",
+           "The run holds, per variant, 1 warm-up and 2 timed batches plus the launches that capture and check",
+           "them: plain per-graph launches, batched plans over 8 internal streams (heuristic, learned), and the",
+           "persistent kernel (heuristic, learned choices), one launch per batch.", "",
+           f"{'kernel':22s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s}"]
+    for k, (c, tot) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{k:22s} {c:7d} {tot / c / 1000:10.1f} {tot / 1e6:10.3f}")
+    if pers:
+        out += ["", "k_persistent launches (ms, in launch order): " + ", ".join(f"{x:.3f}" for x in pers)]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
+    if len(argv) == 3 and argv[1] == "--batch":
+        text = summarise_batch(argv[2])
+        path = os.path.join(ROOT, "profiles", f"gt_kernels_{argv[0]}.txt")
+        with open(path, "w") as f:
+            f.write(text)
+        print(text)
+        return
     if len(argv) != 3:
         raise SystemExit(__doc__)
     workload, passes, d = argv[0], int(argv[1]), argv[2]
