@@ -9,7 +9,8 @@ payload, uniform and geometric-locality graphs of 2^26 vertices and 2^30
 edges, R-MAT scale 26 in natural and permuted order, and R-MAT scale 28
 (2^32 edges: 64-bit look-back words, three partition passes).  Then the
 512-graph uneven batch, planned by the learned policy and replayed from a
-captured HIP graph.  Each case prints its name and its steps as it goes."""
+captured HIP graph, over the internal streams and as one launch of the
+persistent kernel.  Each case prints its name and its steps as it goes."""
 import time
 
 import numpy as np
@@ -64,7 +65,8 @@ def test_full_size_matches_oracle(hip_device, workload):
     say(f"  {workload}: bit-exact, {time.time() - t0:.1f} s in all")
 
 
-def test_batch512_learned_plan_graph_replay_matches_oracle(hip_device):
+@pytest.mark.parametrize("launcher", ["lanes", "persistent"])
+def test_batch512_learned_plan_graph_replay_matches_oracle(hip_device, launcher):
     import paper_2501_06872_amd as gt
     t0 = time.time()
     import concurrent.futures
@@ -75,13 +77,14 @@ def test_batch512_learned_plan_graph_replay_matches_oracle(hip_device):
     with concurrent.futures.ThreadPoolExecutor(16) as pool:  # the generator releases the GIL
         host = list(pool.map(gen.from_spec, specs))
     m_total = sum(int(g[1].size) for g in host)
-    say(f"[case] batch512 (seed 5): 512 graphs, m={m_total}, generated in {time.time() - t0:.1f} s")
+    say(f"[case] batch512 (seed 5), {launcher}: 512 graphs, m={m_total}, generated in {time.time() - t0:.1f} s")
     dev = [(torch.from_numpy(O).to(hip_device), torch.from_numpy(D).to(hip_device),
             torch.from_numpy(P.view(np.int32)).to(hip_device) if P is not None else None) for O, D, P in host]
-    plan = gt.Plan(dev, gt.make_options(policy=gt.POLICY_MLP, model_path=mlp_model.DEFAULT_PATH))
+    flags = gt.FLAG_PERSISTENT if launcher == "persistent" else 0
+    plan = gt.Plan(dev, gt.make_options(policy=gt.POLICY_MLP, model_path=mlp_model.DEFAULT_PATH, flags=flags))
     say(f"  MLP plan built, {time.time() - t0:.1f} s")
     outs = [plan.alloc_out(i, g[2].dtype if g[2] is not None else None) for i, g in enumerate(dev)]
-    plan.run_batched(dev, outs)  # eager warm-up (creates the internal streams)
+    plan.run_batched(dev, outs)  # eager warm-up (creates the internal streams of the lanes)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
