@@ -18,6 +18,7 @@ the HDV table's capacity), and the break-even coverage is where Eq. 3 meets
 Eq. 2 at h = 0.
 
     python -m paper_2501_06872_amd.microbench [--model] [--workloads rmat24p,...]
+        [--levels lds,hot,l2,mall,hbm] [--kinds read,write,atomic,index]
 
 Prints a table on stderr and one JSON line on stdout.
 """
@@ -128,14 +129,16 @@ def main(argv=None):
     ap.add_argument("--model", action="store_true", help="also fit Eq. 2 / Eq. 3 to the unordered Step 1")
     ap.add_argument("--workloads", default="rmat24p,rmat26,rmat26p,uniform26,geom26")
     ap.add_argument("--levels", default=",".join(LEVELS))
+    ap.add_argument("--kinds", default=",".join(KINDS))
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("the microbenchmark needs a GPU")
     dev = torch.device("cuda:0")
     levels = [lv for lv in args.levels.split(",") if lv]
     rates, detail = {}, {}
+    kinds = [k for k in args.kinds.split(",") if k]
     for level in levels:
-        for kind in KINDS:
+        for kind in kinds:
             r, per, ms = measure(level, kind, dev)
             rates[(level, kind)] = r
             detail[f"{level}/{kind}"] = {"g_per_s": round(r / 1e9, 2), "per_thread": per, "ms": round(ms, 3)}

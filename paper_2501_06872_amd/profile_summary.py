@@ -2,6 +2,7 @@
 
     python -m paper_2501_06872_amd.profile_summary <workload> <passes> <dir>
     python -m paper_2501_06872_amd.profile_summary batch512 --batch <dir>
+    python -m paper_2501_06872_amd.profile_summary random-read --fetch <dir> <per> <threads>
 
 <dir> holds the three rocprofv3 databases of one workload, named as the
 commands printed in the summary make them (trace_results.db,
@@ -141,8 +142,40 @@ def summarise_batch(d):
     return "\n".join(out) + "\n"
 
 
+def summarise_random_read(d, per, threads):
+    """FETCH_SIZE of the random-access microbenchmark's HBM reads (each
+    access a 4-byte word at a random place in an 8 GB array, so every one
+    misses every cache): the calibrated bytes per access it implies, for the
+    timed launches of `per` accesses per thread."""
+    con = sqlite3.connect(os.path.join(d, "fetch_results.db"))
+    rows = con.execute("select kernel_name, value from counters_collection where counter_name='FETCH_SIZE'").fetchall()
+    per_disp = [v for k, v in rows if "k_random_global<0>" in k]  # reads of global memory
+    copy = [v for k, v in rows if "copyBuffer" in k]
+    accesses = threads * per
+    timed = sorted(per_disp)[-3:]  # the three timed launches are the largest
+    kib = sum(timed) / len(timed)
+    out = ["# FETCH_SIZE of random 4-byte HBM reads (MI355X, one GPU)", "",
+           "Commands (cd /tmp && export TMPDIR=/tmp PYTHONPATH=<repository root> first):",
+           "  rocprofv3 --pmc FETCH_SIZE -d <dir> -o fetch -- python3 -m paper_2501_06872_amd.microbench "
+           "--levels hbm --kinds read",
+           f"  python -m paper_2501_06872_amd.profile_summary random-read --fetch <dir> {per} {threads}",
+           f"({threads} threads x {per} accesses per thread in each timed launch; `per` from the run's JSON line)", "",
+           f"FETCH_SIZE per timed launch: {kib:.0f} KiB for {accesses} accesses",
+           f"  raw:                {kib * 1024 / accesses:.1f} bytes per access",
+           f"  with the factor 2:  {2 * kib * 1024 / accesses:.1f} bytes per access"]
+    if copy:
+        out.append(f"(a device copy in the same run read {max(copy):.0f} KiB)")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
+    if len(argv) == 5 and argv[1] == "--fetch":
+        text = summarise_random_read(argv[2], int(argv[3]), int(argv[4]))
+        with open(os.path.join(ROOT, "profiles", "gt_fetch_random_read.txt"), "w") as f:
+            f.write(text)
+        print(text)
+        return
     if len(argv) == 3 and argv[1] == "--batch":
         text = summarise_batch(argv[2])
         path = os.path.join(ROOT, "profiles", f"gt_kernels_{argv[0]}.txt")
