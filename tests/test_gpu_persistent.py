@@ -1,7 +1,8 @@
 """GPU: the persistent batched kernel (GT_FLAG_PERSISTENT), one launch that
 drains a device work queue of every graph's phases, against the oracle:
 eager, with payloads, empty and single-pass graphs, offsets validation, the
-learned policy, back-to-back calls, and replays of a captured HIP graph.
+learned policy, back-to-back calls, replays of a captured HIP graph, and an
+invalid graph in a batch (reported, every write inside its outputs).
 Every case prints its name first."""
 import numpy as np
 import pytest
@@ -141,3 +142,39 @@ def test_persistent_refuses_wide_status(hip_device):
     with pytest.raises(gt.GTError) as e:
         gt.Plan(dev, gt.make_options(flags=gt.FLAG_PERSISTENT | gt.FLAG_WIDE_STATUS))
     assert e.value.status == gt.GT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("validate", [False, True])
+def test_persistent_invalid_ids_stay_in_bounds(hip_device, validate):
+    """A batch of an invalid graph (destinations in [n, 1024) and negative
+    ones inside a last bin longer than one k_final item) and a valid one,
+    as one persistent launch: the batch is reported invalid, no write leaves
+    the invalid graph's outputs (canary words after T, S and Q), and the
+    valid graph is still transposed exactly."""
+    import paper_2501_06872_amd as gt
+    n, m = 1000, 16000
+    rng = np.random.default_rng(3)
+    O = np.linspace(0, m, n + 1).astype(np.int64)
+    D = rng.integers(512, 1024, size=m).astype(np.int32)
+    D[::97] = -1
+    for u in range(n):
+        D[O[u]:O[u + 1]].sort()
+    assert np.bincount((D.astype(np.int64) & 1023) >> 9).max() > 8192  # the premise: a big last bin
+    P = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32)
+    good = gen.rmat(12, 8, seed=9)
+    say(f"[case] persistent batch with invalid ids in a big last bin, validate={validate}")
+    dev = [to_dev(O, D, P, hip_device), to_dev(*good, hip_device)]
+    plan = persistent_plan(gt, dev, validate=validate)
+    canary = 0x5A5A5A5A
+    pad = 4096
+    T_big = torch.full((n + 1 + pad,), canary, dtype=torch.int64, device=hip_device)
+    S_big = torch.full((m + pad,), canary, dtype=torch.int32, device=hip_device)
+    Q_big = torch.full((m + pad,), canary, dtype=torch.int32, device=hip_device)
+    outs = [(T_big[:n + 1], S_big[:m], Q_big[:m]), plan.alloc_out(1, None)]
+    plan.run_batched(dev, outs)
+    torch.cuda.synchronize()
+    assert plan.device_status() == gt.GT_ERR_INVALID_GRAPH
+    assert bool((T_big[n + 1:] == canary).all()), "write past T"
+    assert bool((S_big[m:] == canary).all()), "write past S"
+    assert bool((Q_big[m:] == canary).all()), "write past Q"
+    check(outs[1:], [good])
