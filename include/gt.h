@@ -149,8 +149,22 @@ enum { GT_STRATEGY_STABLE = 0, GT_STRATEGY_HLH = 1, GT_STRATEGY_ATOMIC = 2, GT_S
  * to that (gt_plan_set_config's too); gt_plan returns GT_ERR_UNSUPPORTED for
  * a graph that still does not fit (more than two partition passes, m >= 2^31,
  * GT_FLAG_WIDE_STATUS, an unordered strategy). */
+/* GT_FLAG_DEVICE_PLAN (with GT_FLAG_PERSISTENT and GT_POLICY_MLP, at most
+ * 4096 graphs): the learned choice of Section IV-C stays on the device.
+ * gt_plan enqueues the sampling (Step 0), the network and the choice of every
+ * graph on `stream` and returns without synchronising; the workspace it is
+ * given must hold gt_plan_workspace_size() bytes (gt_workspace_size() is
+ * enough) and is the one every gt_transpose_batched call of the plan must
+ * use, since the choices live in it.  Each gt_transpose_batched call lays
+ * the graphs out and builds the persistent kernel's tables in a planning
+ * kernel on the device, so gt_plan and the transpositions capture into one
+ * HIP graph.  Every graph's region is sized for any choice; a graph for
+ * which one possible choice does not fit the persistent kernel is refused
+ * (GT_ERR_UNSUPPORTED).  gt_plan_params reports the heuristic's parameters,
+ * gt_plan_device_choice the learned ones; gt_transpose, gt_transpose_noalloc
+ * and gt_plan_set_config refuse such plans (GT_ERR_UNSUPPORTED). */
 enum { GT_FLAG_WIDE_STATUS = 1, GT_FLAG_FEATURES = 2, GT_FLAG_STEP3_STATIC = 4, GT_FLAG_STEP3_STEAL = 8,
-       GT_FLAG_STEP3_TIMES = 16, GT_FLAG_PERSISTENT = 32 };
+       GT_FLAG_STEP3_TIMES = 16, GT_FLAG_PERSISTENT = 32, GT_FLAG_DEVICE_PLAN = 64 };
 
 typedef struct gt_plan_st *gt_plan_t;
 
@@ -270,6 +284,16 @@ gt_status gt_transpose_noalloc(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out,
  * with a blocking copy.  Errors: GT_ERR_INVALID_ARGUMENT (NULL plan or
  * workspace), GT_ERR_HIP. */
 gt_status gt_plan_device_status(gt_plan_t plan, const void *workspace);
+
+/* GT_FLAG_DEVICE_PLAN plans, after the stream of gt_plan has completed: the
+ * parameters chosen on the device for graph `i` (fine bits, digit width as
+ * given to the layout, tile variant, configuration index or -1 when the
+ * graph's features were outside the network's training range and the
+ * heuristic's choice stands).  Reads 16 bytes of `workspace` with a blocking
+ * copy.  Errors: GT_ERR_INVALID_ARGUMENT (NULL plan or workspace, i out of
+ * range), GT_ERR_UNSUPPORTED (not a device plan), GT_ERR_HIP. */
+gt_status gt_plan_device_choice(gt_plan_t plan, const void *workspace, int32_t i, int32_t *fine_bits,
+                                int32_t *digit_bits, int32_t *variant, int32_t *config);
 
 /* The same status read without a plan (the status word is byte 0 of any
  * workspace the library has used). */

@@ -30,7 +30,8 @@ STRATEGY_STABLE, STRATEGY_HLH, STRATEGY_ATOMIC, STRATEGY_PROBE = range(4)
 
 # Every entry point declared in include/gt.h.
 EXPORTS = ("gt_workspace_size", "gt_plan_scratch_size", "gt_plan_workspace_size", "gt_plan", "gt_transpose",
-           "gt_transpose_batched", "gt_transpose_noalloc", "gt_plan_device_status", "gt_device_status", "gt_plan_params", "gt_plan_packed", "gt_plan_strategy",
+           "gt_transpose_batched", "gt_transpose_noalloc", "gt_plan_device_status", "gt_device_status", "gt_plan_params",
+           "gt_plan_device_choice", "gt_plan_packed", "gt_plan_strategy",
            "gt_plan_step3_times", "gt_plan_destroy", "gt_profile", "gt_profile_read", "gt_plan_features", "gt_config",
            "gt_autotune", "gt_plan_set_config", "gt_mlp_forward", "gt_mlp_gradient", "gt_mlp_adam",
            "gt_random_access", "gt_num_configs", "gt_mlp_num_params", "gt_mlp_work_floats", "gt_status_string")
@@ -81,6 +82,7 @@ def lib():
         L.gt_device_status.argtypes = [vp]
         L.gt_plan_device_status.argtypes = [vp, vp]
         L.gt_plan_params.argtypes = [vp, i32, P(i32), P(i32), P(i32), P(i32)]
+        L.gt_plan_device_choice.argtypes = [vp, vp, i32, P(i32), P(i32), P(i32), P(i32)]
         L.gt_plan_strategy.argtypes = [vp, i32, P(i32)]
         L.gt_plan_packed.argtypes = [vp, i32, P(i32)]
         L.gt_plan_destroy.argtypes = [vp]
@@ -140,7 +142,8 @@ def _check_inputs(offsets, indices, payload):
             raise ValueError("payload must be a contiguous 32-bit tensor with one word per edge")
 
 
-FLAG_WIDE_STATUS, FLAG_FEATURES, FLAG_STEP3_STATIC, FLAG_STEP3_STEAL, FLAG_STEP3_TIMES, FLAG_PERSISTENT = 1, 2, 4, 8, 16, 32
+(FLAG_WIDE_STATUS, FLAG_FEATURES, FLAG_STEP3_STATIC, FLAG_STEP3_STEAL, FLAG_STEP3_TIMES, FLAG_PERSISTENT,
+ FLAG_DEVICE_PLAN) = 1, 2, 4, 8, 16, 32, 64
 
 
 def make_options(policy=POLICY_HEURISTIC, fine_bits=0, digit_bits=0, variant=0, validate=False, seed=0,
@@ -168,7 +171,9 @@ class Plan:
         # what the chosen parameters need (gt_plan_workspace_size)
         opts = options if options is not None else make_options()
         ws = ctypes.c_size_t(0)
-        if opts.strategy == STRATEGY_PROBE:  # the probe runs Step 1 in the transposition layout
+        # the probe runs Step 1 in the transposition layout; a device plan
+        # keeps its choices in the workspace the transpositions use
+        if opts.strategy == STRATEGY_PROBE or (opts.flags & FLAG_DEVICE_PLAN):
             _check(L.gt_workspace_size(arr, self.count, ctypes.byref(ws)), "gt_workspace_size")
         else:
             _check(L.gt_plan_scratch_size(arr, self.count, ctypes.byref(ws)), "gt_plan_scratch_size")
@@ -202,6 +207,14 @@ class Plan:
         _check(lib().gt_plan_params(self.handle, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                     ctypes.byref(d)), "gt_plan_params")
         return dict(fine_bits=a.value, digit_bits=b.value, passes=c.value, variant=d.value)
+
+    def device_choice(self, i=0):
+        """GT_FLAG_DEVICE_PLAN plans: the parameters chosen on the device for
+        graph i (synchronises on the copy)."""
+        a, b, c, d = (ctypes.c_int32() for _ in range(4))
+        _check(lib().gt_plan_device_choice(self.handle, self.workspace.data_ptr(), i, ctypes.byref(a),
+                                           ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)), "gt_plan_device_choice")
+        return dict(fine_bits=a.value, digit_bits=b.value, variant=c.value, config=d.value)
 
     def packed(self, i=0):
         out = ctypes.c_int32()

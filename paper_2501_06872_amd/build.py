@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["gt_api.hip", "gt_kernels.hip", "gt_persistent.hip", "gt_policy.hip", "gt_sample.hip", "gt_mlp.hip", "gt_unordered.hip",
+SOURCES = ["gt_api.hip", "gt_kernels.hip", "gt_persistent.hip", "gt_devplan.hip", "gt_policy.hip", "gt_sample.hip", "gt_mlp.hip", "gt_unordered.hip",
            "gt_microbench.hip"]
 LIB = os.path.join(HERE, "libgt.so")
 OBJDIR = os.path.join(HERE, "_build")

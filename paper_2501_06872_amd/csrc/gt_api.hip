@@ -12,6 +12,8 @@
 
 #include "../../include/gt.h"
 #include "gt_internal.h"
+#include "gt_layout.hpp"
+#include "gt_mlp.h"
 #include "gt_plan.h"
 #include "gt_sample.h"
 #include "gt_unordered.h"
@@ -124,95 +126,7 @@ void finalize_params(GraphPlan &p, size_t base) {
     p.ws_end = unordered_workspace_end(p, base);
     return;
   }
-  const int L = std::max(1, ceil_log2(std::max<int64_t>(p.n, 2)));
-  int fb = std::min(p.fine_bits, kMaxFineBits);
-  fb = std::min(fb, L - 1);
-  fb = std::max(fb, 0);
-  p.fine_bits = fb;
-  if (L - fb > kMaxPasses * 10) fb = L - kMaxPasses * 10;  // at most 3 digits of <= 10 bits
-  p.fine_bits = fb;
-  const int dbits = L - fb;  // >= 1
-  int maxb = std::max(1, std::min(p.digit_bits, 10));
-  maxb = std::max(maxb, (dbits + kMaxPasses - 1) / kMaxPasses);  // widen digits rather than add passes
-  p.passes = (dbits + maxb - 1) / maxb;
-  int rem = dbits, shift = fb, maxbits = 0;
-  // digits as even as possible, the wider ones first (measured: on 2^26-
-  // vertex graphs 9 + 8 bits beat 8 + 9 by 1 % on natural-order R-MAT and
-  // lose 0.3-0.5 % on uniform and permuted graphs)
-  for (int i = 0; i < p.passes; ++i) {
-    const int b = (rem + (p.passes - i) - 1) / (p.passes - i);
-    p.bits[i] = b;
-    p.shift[i] = shift;
-    shift += b;
-    rem -= b;
-    maxbits = std::max(maxbits, b);
-  }
-  p.max_bits = maxbits;
-  p.total_bits = dbits;
-  // fine bits + last digit + source bits <= 48 leaves room for the fine bits
-  // above the 16-bit key in the top of the 32-bit source word
-  p.id_bits = L;
-  p.packed = p.passes == 2 && fb + p.bits[1] + L <= 48 && p.bits[1] <= 10;
-  // The 16-wave tiles have no 10-bit instance (their lane-mask tables would
-  // not fit LDS): such plans use the 8-wave x 16-edge tile for every pass, so
-  // that one tile size holds for the tile sources, the look-back status
-  // words and every pass's grid.
-  p.variant = lsd_variant_for(p.variant, maxbits);
-  p.nbins_total = int64_t(1) << dbits;
-  p.nbins = (p.n + (int64_t(1) << fb) - 1) >> fb;
-  if (p.n == 0) p.nbins = 0;
-  p.tile = lsd_tile_size(p.variant);
-  p.ntiles = (p.m + p.tile - 1) / p.tile;
-
-  size_t off = base;
-  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-  p.off_err = 0;  // one status word for the whole workspace (byte 0)
-  p.off_ticket = take(sizeof(uint32_t) * kMaxPasses);
-  p.off_part = take(sizeof(uint32_t) * (size_t)kHistBlocks * kMaxPasses * kMaxRadix);
-  p.off_digit = take(sizeof(uint64_t) * kMaxPasses * (kMaxRadix + 1));
-  p.off_dtot = take(sizeof(uint64_t) * kMaxPasses * kMaxRadix);
-  p.off_bin = take(sizeof(uint64_t) * (size_t)(p.nbins_total + 1));
-  p.wide_status = p.force_wide || p.m >= (int64_t(1) << 31);
-  // look-back status words of the passes after the first (which places its
-  // tiles with k_hist's per-tile counts)
-  p.off_status = take(p.passes > 1 ? (p.wide_status ? 8 : 4) * (size_t)p.ntiles * ((size_t)1 << p.max_bits) : 0);
-  p.off_tsrc = take(sizeof(int32_t) * (size_t)std::max<int64_t>(p.ntiles, 1));
-  {
-    const size_t r0 = (size_t)1 << p.bits[0];
-    const size_t nt = (size_t)std::max<int64_t>(p.ntiles, 1);
-    p.off_tcnt = take(sizeof(uint16_t) * nt * r0);
-    p.off_tbsum = take(sizeof(uint32_t) * (size_t)std::max<int64_t>(tile_scan_blocks(p.ntiles), 1) * r0);
-    p.off_toff = take(sizeof(uint32_t) * nt * r0);
-  }
-  const size_t m = (size_t)p.m;
-  p.off_a_src = p.off_a_key = p.off_a_pay = 0;
-  p.off_a2_src = p.off_a2_key = p.off_a2_pay = 0;
-  if (p.passes >= 2) {
-    p.off_a_src = take(4 * m);
-    p.off_a_key = take(4 * m);
-    if (p.pay) p.off_a_pay = take(4 * m);
-  }
-  if (p.passes >= 3) {
-    p.off_a2_src = take(4 * m);
-    p.off_a2_key = take(4 * m);
-    if (p.pay) p.off_a2_pay = take(4 * m);
-  }
-  p.off_b_src = take(4 * m);
-  p.off_b_key = take(2 * m);
-  p.off_b_pay = p.pay ? take(4 * m) : 0;
-  const size_t nb = (size_t)std::max<int64_t>(p.nbins, 1);
-  p.max_items = p.nbins + (p.m + final_tile_size() - 1) / final_tile_size();
-  p.off_nch = take(4 * nb);
-  p.off_ibase = take(4 * nb);
-  p.off_ibin = take(16 * (size_t)std::max<int64_t>(p.max_items, 1));  // item descriptors
-  p.off_itotal = take(4 * 4);
-  p.off_sstatus = take(8 * (size_t)((p.nbins + scan_tile_size() - 1) / scan_tile_size() + 1));
-  p.off_cntab = take(4 * (size_t)std::max<int64_t>(p.max_items, 1) * ((size_t)1 << p.fine_bits));
-  p.max_big = std::min<int64_t>(p.nbins, p.m / final_tile_size() + 1);
-  p.off_big = take(4 * (size_t)std::max<int64_t>(p.max_big, 1));
-  p.max_huge = std::min<int64_t>(p.nbins, p.m / (final_tile_size() * kHugeChunks) + 1);
-  p.off_huge = take(4 * (size_t)std::max<int64_t>(p.max_huge, 1));
-  p.ws_end = off;
+  finalize_stable(p, base);
 }
 
 size_t persist_counters_end(int32_t count) {
@@ -221,7 +135,48 @@ size_t persist_counters_end(int32_t count) {
 
 size_t persist_tables_bytes(int32_t count, uint64_t tab_entries) {
   return align_up(sizeof(StableLaunch) * (size_t)count) +
-         align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases) + align_up(4 * (size_t)tab_entries);
+         align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases) + align_up(4 * (size_t)tab_entries) +
+         align_up(2 * sizeof(uint64_t));
+}
+
+DevPlanStage dev_plan_stage(int32_t count) {
+  DevPlanStage d{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 15) & ~size_t(15); return o; };
+  d.params = take(sizeof(float) * kMlpParams);
+  d.fmin = take(sizeof(float) * kMlpIn);
+  d.fmax = take(sizeof(float) * kMlpIn);
+  d.heur = take(sizeof(DevChoice) * (size_t)count);
+  d.fdev = take(sizeof(float *) * (size_t)count);
+  d.staged = off;  // the parts above are copied from the host
+  d.x = take(sizeof(float) * kMlpIn * (size_t)count);
+  d.y = take(sizeof(float) * kMlpOut * (size_t)count);
+  d.total = off;
+  return d;
+}
+
+size_t device_plan_bytes(int32_t count) {
+  return align_up(sizeof(PersistPhase) * (size_t)count * kPersistMaxPhases) +
+         align_up(sizeof(DevChoice) * (size_t)count) + align_up(sizeof(DevGraph) * (size_t)count) +
+         align_up(sizeof(uint32_t) * (size_t)count) + align_up(dev_plan_stage(count).total);
+}
+
+// A device plan's region for one graph: the most any choice the network or
+// the heuristic can make needs; false if one of them does not fit the
+// persistent kernel's bodies.
+static bool device_region(const GraphPlan &heur, size_t *bytes) {
+  size_t most = 0;
+  bool ok = true;
+  for (int c = -1; c < kMlpOut; ++c) {
+    GraphPlan q = heur;
+    if (c >= 0) config_params(c, &q.fine_bits, &q.digit_bits, &q.variant);
+    persist_coerce(q);
+    finalize_stable(q, 0);
+    most = std::max(most, q.ws_end);
+    ok = ok && persist_eligible(q);
+  }
+  *bytes = most;
+  return ok;
 }
 
 uint64_t persist_item_bound(int64_t n, int64_t m) {
@@ -229,27 +184,29 @@ uint64_t persist_item_bound(int64_t n, int64_t m) {
   return 8192 + 8 * ((uint64_t)m / 4096 + 1) + 4 * ((uint64_t)n + 1);
 }
 
-void persist_coerce(GraphPlan &p) {
-  p.variant = 1;
-  p.digit_bits = std::min(p.digit_bits, 9);
-}
-
-bool persist_eligible(const GraphPlan &p) {
-  if (p.strategy != GT_STRATEGY_STABLE) return false;
-  if (p.n == 0 || p.m == 0) return true;
-  return p.variant == 1 && p.tile == lsd_tile_size(1) && p.max_bits <= 9 && p.passes <= 2 && !p.wide_status;
-}
-
 void layout_plan(gt_plan_st *plan) {
   size_t base = plan->persistent ? align_up(persist_counters_end(plan->count)) : kAlign;  // byte 0: status word
-  for (GraphPlan &p : plan->graphs) {
+  if (plan->device_plan) plan->graph_base.assign(plan->count, 0);
+  for (int32_t i = 0; i < plan->count; ++i) {
+    GraphPlan &p = plan->graphs[i];
     finalize_params(p, base);
-    base = align_up(p.ws_end);
+    if (plan->device_plan) {  // a region for any choice
+      size_t most = 0;
+      (void)device_region(p, &most);
+      plan->graph_base[i] = base;
+      base = align_up(base + std::max(most, p.ws_end - base));
+    } else {
+      base = align_up(p.ws_end);
+    }
   }
   if (plan->persistent) {
     uint64_t items = 0;
     PersistPhase buf[kPersistMaxPhases];
     for (const GraphPlan &p : plan->graphs) {
+      if (plan->device_plan) {  // any choice
+        items += persist_item_bound(p.n, p.m);
+        continue;
+      }
       const int k = persist_phases(p, nullptr, nullptr, 0, plan->validate, buf);
       for (int j = 0; j < k; ++j) items += buf[j].nitems;
     }
@@ -257,7 +214,19 @@ void layout_plan(gt_plan_st *plan) {
     plan->off_pdesc = base;
     plan->off_pphase = base + align_up(sizeof(StableLaunch) * (size_t)plan->count);
     plan->off_ptab = plan->off_pphase + align_up(sizeof(PersistPhase) * (size_t)plan->count * kPersistMaxPhases);
+    plan->off_pmeta = plan->off_ptab + align_up(4 * (size_t)plan->ptab_entries);
     base += persist_tables_bytes(plan->count, plan->ptab_entries);
+  }
+  if (plan->device_plan) {
+    const size_t n = (size_t)plan->count;
+    plan->off_ptmp = base;
+    plan->off_pchoice = plan->off_ptmp + align_up(sizeof(PersistPhase) * n * kPersistMaxPhases);
+    plan->off_pgraph = plan->off_pchoice + align_up(sizeof(DevChoice) * n);
+    plan->off_porder = plan->off_pgraph + align_up(sizeof(DevGraph) * n);
+    plan->off_pdp = plan->off_porder + align_up(sizeof(uint32_t) * n);
+    plan->off_psamp = plan->off_pdp + align_up(dev_plan_stage(plan->count).total);
+    base = plan->off_psamp;
+    for (const GraphPlan &p : plan->graphs) base += align_up(sample_scratch_bytes(p.n, p.m));
   }
   plan->ws_bytes = std::max<size_t>(base, 256);
 }
@@ -305,102 +274,6 @@ hipError_t Profiler::begin(const char *name, hipStream_t st) {
 hipError_t Profiler::end(hipStream_t st) {
   if (!on || recs.empty()) return hipSuccess;
   return hipEventRecord(recs.back().stop, st);
-}
-
-// The arguments of every kernel of a stable transposition.
-StableLaunch stable_launch(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate) {
-  StableLaunch L{};
-  L.O = g.offsets; L.D = g.indices; L.n = p.n; L.m = p.m;
-  L.ntiles = p.ntiles; L.tile = p.tile; L.nbins_total = p.nbins_total;
-  L.passes = p.passes; L.radix0 = 1 << p.bits[0]; L.variant = p.variant;
-  L.pay = p.pay; L.wide = p.wide_status; L.validate = validate;
-  L.err = reinterpret_cast<uint32_t *>(ws);
-  L.ticket = reinterpret_cast<uint32_t *>(ws + p.off_ticket);
-  L.part = reinterpret_cast<uint32_t *>(ws + p.off_part);
-  L.digit = reinterpret_cast<uint64_t *>(ws + p.off_digit);
-  L.bins = reinterpret_cast<uint64_t *>(ws + p.off_bin);
-  L.status = reinterpret_cast<uint32_t *>(ws + p.off_status);
-  L.status_words = (uint64_t)p.ntiles * ((uint64_t)1 << p.max_bits) * (p.wide_status ? 2 : 1);
-  L.tsrc = reinterpret_cast<int32_t *>(ws + p.off_tsrc);
-  L.tcnt = reinterpret_cast<uint16_t *>(ws + p.off_tcnt);
-  L.tbsum = reinterpret_cast<uint32_t *>(ws + p.off_tbsum);
-  L.toff = reinterpret_cast<uint32_t *>(ws + p.off_toff);
-  L.dtot = reinterpret_cast<uint64_t *>(ws + p.off_dtot);
-  L.h.passes = p.passes;
-  for (int i = 0; i < p.passes; ++i) { L.h.shift[i] = p.shift[i]; L.h.bits[i] = p.bits[i]; }
-  // histogram workgroups take contiguous ranges of the first pass's tiles,
-  // at most kHistBlocks of them: a small graph neither launches nor sums
-  // partial histograms it has no edges for
-  L.hist_blocks = (int)std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles));
-  const int32_t *cur_src = nullptr;
-  const uint32_t *cur_key = nullptr, *cur_pay = nullptr;
-  for (int pass = 0; pass < p.passes; ++pass) {
-    const bool first = pass == 0, last = pass == p.passes - 1;
-    LsdArgs &a = L.lsd[pass];
-    a.O = g.offsets; a.D = g.indices; a.P = g.payload; a.tile_src0 = L.tsrc; a.tile_off = L.toff;
-    a.in_src = cur_src; a.in_key = cur_key; a.in_pay = cur_pay;
-    const bool pk = p.packed && (first != last);
-    L.pk[pass] = pk;
-    if (pk && last) a.in_key16 = reinterpret_cast<const uint16_t *>(cur_key);
-    if (last) {
-      a.out_src = reinterpret_cast<int32_t *>(ws + p.off_b_src);
-      a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_b_key);
-      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + p.off_b_pay) : nullptr;
-    } else {
-      const bool use_a2 = (pass == 1);
-      a.out_src = reinterpret_cast<int32_t *>(ws + (use_a2 ? p.off_a2_src : p.off_a_src));
-      a.out_key32 = reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_key : p.off_a_key));
-      if (pk) a.out_key16 = reinterpret_cast<uint16_t *>(ws + p.off_a_key);
-      a.out_pay = p.pay ? reinterpret_cast<uint32_t *>(ws + (use_a2 ? p.off_a2_pay : p.off_a_pay)) : nullptr;
-    }
-    a.shift = p.shift[pass];
-    a.bits = p.bits[pass];
-    a.digit_start = L.digit + pass * (kMaxRadix + 1);
-    a.status = L.status;
-    a.ticket = L.ticket + pass;
-    a.m = p.m; a.n = p.n;
-    a.fine_shift = p.fine_bits;
-    a.lower_bits = p.total_bits - p.bits[p.passes - 1];
-    a.fine_mask = (1u << p.fine_bits) - 1u;
-    a.bin_start = L.bins;
-    if (pk) {
-      a.pk_lo = 16 - p.bits[1];
-      a.pk_src_bits = p.id_bits;
-      a.pk_dshift = p.shift[1];
-      a.pk_dbits = p.bits[1];
-      if (last) {  // the packed key holds the digit at bit pk_lo
-        a.shift = a.pk_lo;
-        a.prev_digit_start = L.digit;
-        a.prev_bits = p.bits[0];
-      }
-    }
-    cur_src = a.out_src;
-    cur_key = a.out_key32;
-    cur_pay = a.out_pay;
-  }
-  FinalArgs &f = L.f;
-  f.in_src = reinterpret_cast<const int32_t *>(ws + p.off_b_src);
-  f.in_key = reinterpret_cast<const uint16_t *>(ws + p.off_b_key);
-  f.in_pay = p.pay ? reinterpret_cast<const uint32_t *>(ws + p.off_b_pay) : nullptr;
-  f.bin_start = L.bins;
-  f.T = out.offsets; f.S = out.indices; f.Q = out.payload;
-  f.n = p.n; f.m = p.m; f.nbins = p.nbins; f.fine_bits = p.fine_bits;
-  f.nch = reinterpret_cast<uint32_t *>(ws + p.off_nch);
-  f.item_base = reinterpret_cast<uint32_t *>(ws + p.off_ibase);
-  f.item_desc = reinterpret_cast<uint4 *>(ws + p.off_ibin);
-  f.total_items = reinterpret_cast<uint32_t *>(ws + p.off_itotal);
-  f.cntab = reinterpret_cast<uint32_t *>(ws + p.off_cntab);
-  f.bigbins = reinterpret_cast<uint32_t *>(ws + p.off_big);
-  f.nbig = f.total_items + 2;
-  f.hugebins = reinterpret_cast<uint32_t *>(ws + p.off_huge);
-  f.nhuge = f.total_items + 3;
-  f.err = L.err;
-  L.sstatus = reinterpret_cast<uint32_t *>(ws + p.off_sstatus);
-  L.scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
-  L.max_items = p.max_items;
-  L.max_big = p.max_big;
-  L.max_huge = p.max_huge;
-  return L;
 }
 
 // Enqueue the whole transposition of one graph.
@@ -559,7 +432,10 @@ gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_
 // Persistent plans: every graph must fit the persistent kernel's bodies;
 // the pinned staging buffer, its event and the launch's grid.
 gt_status gt::persist_staging(gt_plan_st *plan) {
-  const size_t need = persist_tables_bytes(plan->count, plan->ptab_entries);
+  // host plans stage the tables; device plans the graphs' pointers and the
+  // queue order (the planning kernel builds the tables)
+  const size_t need = plan->device_plan ? plan->off_porder + sizeof(uint32_t) * (size_t)plan->count - plan->off_pgraph
+                                        : persist_tables_bytes(plan->count, plan->ptab_entries);
   if (plan->pk_host != nullptr && plan->pk_bytes >= need) return GT_OK;
   if (plan->pk_host != nullptr) {
     if (plan->pk_event != nullptr && hipEventSynchronize(plan->pk_event) != hipSuccess) return GT_ERR_HIP;
@@ -596,9 +472,12 @@ static gt_status persist_setup(gt_plan_st *plan) {
 }
 
 gt_plan_st::~gt_plan_st() {
-  if (pk_event) (void)hipEventSynchronize(pk_event);  // no copy still reads the staging buffer
+  if (pk_event) (void)hipEventSynchronize(pk_event);  // no copy still reads the staging buffers
+  if (dp_event) (void)hipEventSynchronize(dp_event);
   if (pk_event) (void)hipEventDestroy(pk_event);
+  if (dp_event) (void)hipEventDestroy(dp_event);
   if (pk_host) (void)hipHostFree(pk_host);
+  if (dp_host) (void)hipHostFree(dp_host);
   for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : lane_events) (void)hipEventDestroy(e);
   if (fork_event) (void)hipEventDestroy(fork_event);
@@ -632,6 +511,7 @@ gt_status gt_workspace_size(const gt_csr_t *graphs, int32_t count, size_t *bytes
   uint64_t items = 0;
   for (int32_t i = 0; i < count; ++i) items += persist_item_bound(graphs[i].n, graphs[i].m);
   total += align_up(persist_counters_end(count)) + persist_tables_bytes(count, (items >> kPersistTabShift) + 2);
+  total += device_plan_bytes(count);
   total += align_up(plan_scratch_bytes(graphs, count));
   *bytes_out = total;
   return GT_OK;
@@ -666,10 +546,15 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
         (o.digit_bits != 0 && (o.digit_bits < 4 || o.digit_bits > 10)) || o.variant < 0 || o.variant > 4)
       return GT_ERR_UNSUPPORTED;
   }
+  const bool device_plan = (o.flags & GT_FLAG_DEVICE_PLAN) != 0;
+  if (device_plan && (!(o.flags & GT_FLAG_PERSISTENT) || o.policy != GT_POLICY_MLP ||
+                      o.strategy != GT_STRATEGY_STABLE || (o.flags & GT_FLAG_WIDE_STATUS) || count > kDevPlanMaxGraphs))
+    return GT_ERR_UNSUPPORTED;
   gt_plan_st *plan = new (std::nothrow) gt_plan_st();
   if (!plan) return GT_ERR_INVALID_ARGUMENT;
   plan->count = count;
   plan->validate = o.validate != 0;
+  plan->device_plan = device_plan;
   plan->graphs.resize(count);
   gt_status st = choose_params(plan, graphs, count, o, workspace, workspace_bytes, (hipStream_t)stream);
   if (st != GT_OK) { delete plan; return st; }
@@ -684,6 +569,15 @@ gt_status gt_plan(const gt_csr_t *graphs, int32_t count, const gt_options_t *opt
   layout_plan(plan);
   if (plan->persistent) {
     st = persist_setup(plan);
+    if (st != GT_OK) { delete plan; return st; }
+  }
+  if (device_plan) {
+    for (const GraphPlan &p : plan->graphs) {
+      size_t most = 0;
+      if (!device_region(p, &most)) { delete plan; return GT_ERR_UNSUPPORTED; }
+    }
+    if (workspace == nullptr || workspace_bytes < plan->ws_bytes) { delete plan; return GT_ERR_WORKSPACE_TOO_SMALL; }
+    st = device_plan_setup(plan, graphs, o, static_cast<char *>(workspace), (hipStream_t)stream);
     if (st != GT_OK) { delete plan; return st; }
   }
   *plan_out = plan;
@@ -703,6 +597,7 @@ static gt_status check_io(const GraphPlan &p, const gt_csr_t *g, const gt_csc_t 
 gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t workspace_bytes,
                        void *stream) {
   if (plan == nullptr || plan->count != 1 || workspace == nullptr) return GT_ERR_INVALID_ARGUMENT;
+  if (plan->device_plan) return GT_ERR_UNSUPPORTED;  // its choice is on the device: gt_transpose_batched
   const GraphPlan &p = plan->graphs[0];
   gt_status s = check_io(p, g, out);
   if (s != GT_OK) return s;
@@ -714,6 +609,7 @@ gt_status gt_transpose(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, void *w
 gt_status gt_transpose_noalloc(gt_plan_t plan, const gt_csr_t *g, gt_csc_t *out, uint32_t *status_out,
                                void *stream) {
   if (plan == nullptr || plan->count != 1) return GT_ERR_INVALID_ARGUMENT;
+  if (plan->device_plan) return GT_ERR_UNSUPPORTED;
   const GraphPlan &p = plan->graphs[0];
   gt_status s = check_io(p, g, out);
   if (s != GT_OK) return s;
@@ -753,6 +649,20 @@ gt_status gt_device_status(const void *workspace) {
   if (err & (kErrBadIndex | kErrBadOffsets)) return GT_ERR_INVALID_GRAPH;
   if (err & kErrOverflow) return GT_ERR_COUNTER_OVERFLOW;
   if (err & kErrStall) return GT_ERR_STALLED;
+  return GT_OK;
+}
+
+gt_status gt_plan_device_choice(gt_plan_t plan, const void *workspace, int32_t i, int32_t *fine_bits,
+                                int32_t *digit_bits, int32_t *variant, int32_t *config) {
+  if (plan == nullptr || workspace == nullptr || i < 0 || i >= plan->count) return GT_ERR_INVALID_ARGUMENT;
+  if (!plan->device_plan) return GT_ERR_UNSUPPORTED;
+  DevChoice c{};
+  const char *src = static_cast<const char *>(workspace) + plan->off_pchoice + sizeof(DevChoice) * (size_t)i;
+  if (hipMemcpy(&c, src, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return GT_ERR_HIP;
+  if (fine_bits) *fine_bits = c.fine_bits;
+  if (digit_bits) *digit_bits = c.digit_bits;
+  if (variant) *variant = c.variant;
+  if (config) *config = c.config;
   return GT_OK;
 }
 

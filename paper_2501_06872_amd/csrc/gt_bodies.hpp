@@ -186,8 +186,6 @@ __device__ __forceinline__ void hist_body(const int32_t *__restrict__ D, int64_t
 // tile's offset within each digit.  Offsets are kept in 32 bits: the offset
 // of a tile that holds edges of digit d is below the digit's total, so below
 // 2^32 for every accepted edge count.
-constexpr int kTileBlk = 64;
-
 template <int NT>
 __device__ __forceinline__ void tile_bsum_body(const uint16_t *__restrict__ tilecnt, int64_t ntiles, int radix,
                                                int64_t nblk, uint32_t *__restrict__ bsum, int64_t b) {

@@ -138,8 +138,7 @@ constexpr uint32_t kNoDep = 0xFFFFFFFFu;
 struct PersistArgs {
   const StableLaunch *graphs;
   const PersistPhase *phases;
-  int32_t nphases;
-  uint64_t total;              // tickets in the queue
+  const uint64_t *meta;  // [0] tickets in the queue, [1] phases (written by the host or by k_persist_plan)
   // tab[i]: the phase holding ticket i << kPersistTabShift (i <= total >> shift)
   const uint32_t *tab;
   unsigned long long *ticket;  // next ticket
@@ -152,20 +151,70 @@ constexpr int kPersistTabShift = 4;
 constexpr uint32_t kErrStall = 8u;
 // threads per workgroup of the persistent kernel, and its LDS
 constexpr int kPersistThreads = 512;
+
+// ---- Planning on the device (GT_FLAG_DEVICE_PLAN): the learned choice of
+// every graph stays in the workspace, and every call lays the graphs out and
+// builds the persistent kernel's tables in a planning kernel.
+struct DevChoice {
+  int32_t fine_bits, digit_bits, variant;
+  int32_t config;  // configuration index of the learned choice, -1: the heuristic's
+};
+struct DevGraph {
+  int64_t n, m;
+  const int64_t *offsets;
+  const int32_t *indices;
+  const uint32_t *payload;
+  int64_t *out_offsets;
+  int32_t *out_indices;
+  uint32_t *out_payload;
+  uint64_t base;  // the graph's workspace region (sized for any choice)
+};
+struct DevPlanArgs {
+  const DevGraph *graphs;   // [count]
+  const uint32_t *order;    // [count] graphs by edge count, the largest first (ties: index)
+  const DevChoice *choice;  // [count]
+  int32_t count;
+  bool validate;
+  int32_t grid;             // workgroups of the persistent launch (items per ticket)
+  char *ws;
+  StableLaunch *desc;       // [count]
+  PersistPhase *tmp;        // [count][kPersistMaxPhases] every graph's phases
+  PersistPhase *table;      // [count * kPersistMaxPhases] the queue's phases
+  uint32_t *tab;            // ticket -> phase table
+  uint64_t *meta;           // tickets, phases
+};
+constexpr int kDevPlanMaxGraphs = 4096;
+hipError_t launch_gather_features(const float *const *fdev, int32_t count, float *x, hipStream_t st);
+hipError_t launch_choose(const float *x, const float *y, const float *fmin, const float *fmax, int32_t count,
+                         const DevChoice *heur, DevChoice *out, hipStream_t st);
+hipError_t launch_persist_plan(const DevPlanArgs &a, hipStream_t st);
 size_t persistent_lds_bytes();
 // workgroups of the persistent kernel one CU holds at once (0 on error)
 int persistent_workgroups_per_cu();
 hipError_t launch_persistent(const PersistArgs &a, int grid, hipStream_t st);
 
-int64_t lsd_tile_size(int variant);
+// Edges per partition tile of a tile variant (waves x edges per lane x 64).
+__host__ __device__ inline int64_t lsd_tile_size(int variant) {
+  switch (variant) {
+    case 2: return 16 * 64 * 8;
+    case 3: return 8 * 64 * 8;
+    case 4: return 16 * 64 * 16;
+    default: return 8 * 64 * 16;
+  }
+}
 // The tile variant that runs digits of up to max_bits bits (variants without
 // an instance for that width map to variant 1).
-int lsd_variant_for(int variant, int max_bits);
+__host__ __device__ inline int lsd_variant_for(int variant, int max_bits) {
+  if (variant < 1 || variant > 4) return 1;
+  if ((variant == 2 || variant == 4) && max_bits > 9) return 1;
+  return variant;
+}
 hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, bool pay, bool last, bool packed,
                       bool wide_status,
                       hipStream_t st);
-int64_t final_tile_size();
-int64_t scan_tile_size();
+// Edges per k_final work item; entries per tile of the u32 scan.
+__host__ __device__ inline int64_t final_tile_size() { return 8 * 64 * 16; }
+__host__ __device__ inline int64_t scan_tile_size() { return 256 * 16; }
 hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st);
 hipError_t launch_item_map(const FinalArgs &a, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint32_t *status, uint32_t *ticket,
@@ -188,7 +237,8 @@ hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h
 // Column prefix of tilecnt -> tileoff[ntiles][radix] (uint32) and the first
 // pass's digit totals (totals0[radix]); bsum holds tile_scan_blocks(ntiles)
 // * radix words.
-int64_t tile_scan_blocks(int64_t ntiles);
+constexpr int kTileBlk = 64;  // tiles per block of the first pass's tile prefix
+__host__ __device__ inline int64_t tile_scan_blocks(int64_t ntiles) { return (ntiles + kTileBlk - 1) / kTileBlk; }
 hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, uint32_t *bsum, uint64_t *totals0,
                             uint32_t *tileoff, hipStream_t st);
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,

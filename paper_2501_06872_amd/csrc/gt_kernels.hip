@@ -169,21 +169,6 @@ static hipError_t launch_lsd_t(const LsdArgs &a, bool csr_in, bool pay, bool las
               : launch_lsd_w<WAVES, ITEMS, RBITS, uint32_t>(a, csr_in, pay, last, pk, st);
 }
 
-int64_t lsd_tile_size(int variant) {
-  switch (variant) {
-    case 2: return 16 * kWave * 8;
-    case 3: return 8 * kWave * 8;
-    case 4: return 16 * kWave * 16;
-    default: return 8 * kWave * 16;
-  }
-}
-
-int lsd_variant_for(int variant, int max_bits) {
-  if (variant < 1 || variant > 4) return 1;
-  if ((variant == 2 || variant == 4) && max_bits > 9) return 1;
-  return variant;
-}
-
 // Every (variant, digit width) pair runs an instance whose tile is
 // lsd_tile_size(variant); a pair without one is refused rather than run with
 // another tile size than the plan sized its buffers for.
@@ -209,8 +194,6 @@ hipError_t launch_lsd(int variant, int rbits, const LsdArgs &a, bool csr_in, boo
 #undef GT_V
 }
 
-int64_t final_tile_size() { return 8 * kWave * 16; }
-
 hipError_t launch_bin_items(const FinalArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(k_bin_items, dim3((unsigned)((a.nbins + 255) / 256)), dim3(256), 0, st, a.bin_start, a.nbins,
                      final_tile_size(), a.nch, a.T, a.n, a.m);
@@ -232,8 +215,6 @@ hipError_t launch_big_scan(const FinalArgs &a, int64_t max_big, int64_t max_huge
   }
   return hipGetLastError();
 }
-
-int64_t scan_tile_size() { return 256 * 16; }
 
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, uint32_t *status, uint32_t *ticket,
                            uint32_t *total, hipStream_t st) {
@@ -314,8 +295,6 @@ hipError_t launch_hist(const int32_t *D, int64_t m, int64_t n, const HistArgs &h
   }
   return hipGetLastError();
 }
-
-int64_t tile_scan_blocks(int64_t ntiles) { return (ntiles + kTileBlk - 1) / kTileBlk; }
 
 hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, uint32_t *bsum, uint64_t *totals0,
                             uint32_t *tileoff, hipStream_t st) {

@@ -16,7 +16,7 @@ hipError_t mlp_forward(const float *params, const float *x, int batch, float *y,
 
 // Configuration c of the learned/autotuned choice:
 // fine_bits = 6 + c / 8, variant = 1 + (c / 2) % 4, digit_bits = (c % 2) ? 10 : 8.
-inline void config_params(int c, int *fine_bits, int *digit_bits, int *variant) {
+__host__ __device__ inline void config_params(int c, int *fine_bits, int *digit_bits, int *variant) {
   *fine_bits = 6 + c / 8;
   *variant = 1 + (c / 2) % 4;
   *digit_bits = (c % 2) ? 10 : 8;

@@ -186,10 +186,10 @@ __device__ __forceinline__ void persist_publish(const PersistArgs &pa, int32_t p
 
 // The phase holding ticket t: the coarse table brackets it, a binary search
 // inside the bracket (usually empty) finds it.
-__device__ __forceinline__ int32_t persist_phase_of(const PersistArgs &pa, unsigned long long t) {
+__device__ __forceinline__ int32_t persist_phase_of(const PersistArgs &pa, int32_t nphases, unsigned long long t) {
   const uint64_t b = t >> kPersistTabShift;
   int32_t lo = (int32_t)pa.tab[b], hi = (int32_t)pa.tab[b + 1] + 1;
-  if (hi > pa.nphases) hi = pa.nphases;
+  if (hi > nphases) hi = nphases;
   while (hi - lo > 1) {
     const int32_t mid = (lo + hi) >> 1;
     if (pa.phases[mid].start <= t) lo = mid; else hi = mid;
@@ -205,6 +205,8 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
   __shared__ unsigned long long s_ticket;
   __shared__ int32_t s_phase;
   const int tid = threadIdx.x;
+  const unsigned long long total = pa.meta[0];
+  const int32_t nphases = (int32_t)pa.meta[1];
   // thread 0: the next ticket (taken while the current one runs), finished
   // items not yet published, and the last phase whose completion this
   // workgroup has acquired
@@ -218,13 +220,13 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
       if (!have_next) next = atomicAdd(pa.ticket, 1ull);
       have_next = false;
       s_ticket = next;
-      if (next < pa.total) s_phase = persist_phase_of(pa, next);
+      if (next < total) s_phase = persist_phase_of(pa, nphases, next);
     }
     __syncthreads();
     // uniform across the workgroup: read into scalar registers, so that the
     // phase and graph descriptors are read with scalar loads
     const unsigned long long t = uniform_u64(s_ticket);
-    if (t >= pa.total) break;
+    if (t >= total) break;
     const int32_t ph = __builtin_amdgcn_readfirstlane(s_phase);
     const PersistPhase &P = pa.phases[ph];
     if (tid == 0) {
@@ -283,7 +285,7 @@ int persistent_workgroups_per_cu() {
 }
 
 hipError_t launch_persistent(const PersistArgs &a, int grid, hipStream_t st) {
-  if (a.total == 0 || grid <= 0) return hipSuccess;
+  if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_persistent, dim3((unsigned)grid), dim3(kPersistThreads), sizeof(PersistShared), st, a);
   return hipGetLastError();
 }

@@ -105,6 +105,20 @@ struct gt_plan_st {
   hipEvent_t pk_event = nullptr;  // the last copy out of pk_host
   bool pk_pending = false;
   int pk_grid = 0;  // workgroups of the persistent launch
+  size_t off_pmeta = 0;  // the queue's size: tickets, phases
+  // GT_FLAG_DEVICE_PLAN: the learned choice is made on the device and kept
+  // in the workspace (off_pchoice); every graph owns a region sized for any
+  // choice (graph_base); each batched call lays the graphs out and builds
+  // the tables on the device from the graphs' pointers (off_pgraph) and the
+  // queue order (off_porder).  dp_host stages the network and the heuristic
+  // choices for the planning kernels (copied once, by gt_plan).
+  bool device_plan = false;
+  std::vector<uint64_t> graph_base;
+  std::vector<uint32_t> order;
+  size_t off_ptmp = 0, off_pchoice = 0, off_pgraph = 0, off_porder = 0, off_pdp = 0, off_psamp = 0;
+  void *dp_host = nullptr;
+  size_t dp_bytes = 0;
+  hipEvent_t dp_event = nullptr;
   ~gt_plan_st();
 };
 
@@ -117,7 +131,6 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
                         void *workspace, size_t workspace_bytes, hipStream_t st);
 gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate,
                         bool reset_status, Profiler *prof, hipStream_t st);
-StableLaunch stable_launch(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, bool validate);
 size_t unordered_workspace_end(GraphPlan &p, size_t base);
 gt_status enqueue_unordered(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &out, char *ws, Profiler *prof,
                             hipStream_t st);
@@ -128,18 +141,27 @@ gt_status enqueue_batched(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc
 constexpr size_t kPersistDoneOff = 16;
 size_t persist_counters_end(int32_t count);
 size_t persist_tables_bytes(int32_t count, uint64_t tab_entries);
+// Device plans: the regions beyond the persistent tables (every graph's
+// phases, choices, pointers, queue order, the network's staging and its
+// inputs and outputs).
+size_t device_plan_bytes(int32_t count);
+// Device-plan staging region: network parameters, input ranges, heuristic
+// choices, feature pointers, network inputs and outputs (byte offsets).
+struct DevPlanStage {
+  size_t params, fmin, fmax, heur, fdev, x, y, staged, total;
+};
+DevPlanStage dev_plan_stage(int32_t count);
 // Items of all phases of a graph of n vertices and m edges, at most, for any
 // parameters (sizes the ticket -> phase table before a plan exists).
 uint64_t persist_item_bound(int64_t n, int64_t m);
+// Device plans: stage the network and the heuristic choices, enqueue the
+// sampling, the network and the choice (no host synchronisation).
+gt_status device_plan_setup(gt_plan_st *plan, const gt_csr_t *graphs, const gt_options_t &opt, char *ws,
+                            hipStream_t st);
 // (Re)allocate a persistent plan's pinned staging buffer for its tables.
 gt_status persist_staging(gt_plan_st *plan);
-int persist_phases(const GraphPlan &p, const StableLaunch *L, const gt_csc_t *out, int32_t g, bool validate,
-                   PersistPhase *ph);
-// Variant-1 tiles, digits of at most 9 bits (the persistent kernel's bodies).
-void persist_coerce(GraphPlan &p);
-bool persist_eligible(const GraphPlan &p);
 // Offsets of every graph's region (and of a persistent plan's tables); sets
-// plan->ws_bytes.
+// plan->ws_bytes.  (The per-graph layout itself: gt_layout.hpp.)
 void layout_plan(gt_plan_st *plan);
 
 }  // namespace gt

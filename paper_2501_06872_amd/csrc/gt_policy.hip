@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gt_internal.h"
+#include "gt_layout.hpp"
 #include "gt_mlp.h"
 #include "gt_plan.h"
 #include "gt_sample.h"
@@ -136,6 +137,67 @@ static gt_status mlp_choose(gt_plan_st *plan, int32_t count, const MlpModel &mdl
   return GT_OK;
 }
 
+gt_status device_plan_setup(gt_plan_st *plan, const gt_csr_t *graphs, const gt_options_t &opt, char *ws,
+                            hipStream_t st) {
+  const int32_t count = plan->count;
+  const DevPlanStage d = dev_plan_stage(count);
+  if (hipHostMalloc(&plan->dp_host, d.staged, hipHostMallocDefault) != hipSuccess) {
+    plan->dp_host = nullptr;
+    return GT_ERR_HIP;
+  }
+  plan->dp_bytes = d.staged;
+  if (hipEventCreateWithFlags(&plan->dp_event, hipEventDisableTiming) != hipSuccess) {
+    plan->dp_event = nullptr;
+    return GT_ERR_HIP;
+  }
+  char *h = static_cast<char *>(plan->dp_host);
+  char *dev = ws + plan->off_pdp;
+  DevChoice *heur = reinterpret_cast<DevChoice *>(h + d.heur);
+  for (int32_t i = 0; i < count; ++i) {
+    const GraphPlan &p = plan->graphs[i];
+    heur[i] = DevChoice{p.fine_bits, p.digit_bits, p.variant, -1};
+  }
+  // the queue order: graphs by edge count, the largest first (ties: index)
+  plan->order.resize(count);
+  for (int32_t i = 0; i < count; ++i) plan->order[i] = (uint32_t)i;
+  std::stable_sort(plan->order.begin(), plan->order.end(),
+                   [&](uint32_t a, uint32_t b) { return plan->graphs[a].m > plan->graphs[b].m; });
+  DevChoice *choice = reinterpret_cast<DevChoice *>(ws + plan->off_pchoice);
+  MlpModel mdl;
+  if (!load_model(opt.model_path, mdl)) {  // no network: the heuristic's choices
+    if (hipMemcpyAsync(dev + d.heur, h + d.heur, sizeof(DevChoice) * (size_t)count, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(choice, dev + d.heur, sizeof(DevChoice) * (size_t)count, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        hipEventRecord(plan->dp_event, st) != hipSuccess)
+      return GT_ERR_HIP;
+    return GT_OK;
+  }
+  memcpy(h + d.params, mdl.params.data(), sizeof(float) * kMlpParams);
+  memcpy(h + d.fmin, mdl.fmin.data(), sizeof(float) * kMlpIn);
+  memcpy(h + d.fmax, mdl.fmax.data(), sizeof(float) * kMlpIn);
+  // Step 0 of every graph into its own sampling scratch
+  float **fdev = reinterpret_cast<float **>(h + d.fdev);
+  char *samp = ws + plan->off_psamp;
+  for (int32_t i = 0; i < count; ++i) {
+    if (enqueue_sampling(graphs[i].offsets, graphs[i].indices, graphs[i].n, graphs[i].m,
+                         graphs[i].payload != nullptr, opt.seed ? opt.seed : 0x5eedull, samp, &fdev[i], st) !=
+        hipSuccess)
+      return GT_ERR_HIP;
+    samp += align256(sample_scratch_bytes(graphs[i].n, graphs[i].m));
+  }
+  float *x = reinterpret_cast<float *>(dev + d.x);
+  float *y = reinterpret_cast<float *>(dev + d.y);
+  if (hipMemcpyAsync(dev, h, d.staged, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(plan->dp_event, st) != hipSuccess ||
+      launch_gather_features(reinterpret_cast<const float *const *>(dev + d.fdev), count, x, st) != hipSuccess ||
+      mlp_forward(reinterpret_cast<const float *>(dev + d.params), x, count, y, st) != hipSuccess ||
+      launch_choose(x, y, reinterpret_cast<const float *>(dev + d.fmin), reinterpret_cast<const float *>(dev + d.fmax),
+                    count, reinterpret_cast<const DevChoice *>(dev + d.heur), choice, st) != hipSuccess)
+    return GT_ERR_HIP;
+  return GT_OK;
+}
+
 gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count, const gt_options_t &opt,
                         void *workspace, size_t workspace_bytes, hipStream_t st) {
   for (int32_t i = 0; i < count; ++i) {
@@ -160,7 +222,8 @@ gt_status choose_params(gt_plan_st *plan, const gt_csr_t *graphs, int32_t count,
   }
   // HEURISTIC and FIXED choose from the sizes alone: no device work and no
   // synchronisation unless features were asked for.
-  if (opt.policy == GT_POLICY_MLP || (opt.flags & GT_FLAG_FEATURES)) {
+  // a device plan samples and chooses on the device (device_plan_setup)
+  if ((opt.policy == GT_POLICY_MLP || (opt.flags & GT_FLAG_FEATURES)) && !(opt.flags & GT_FLAG_DEVICE_PLAN)) {
     char *base = scratch_base(graphs, count, workspace, workspace_bytes);
     if (base == nullptr) return GT_ERR_WORKSPACE_TOO_SMALL;
     gt_status s = sample_features(plan, graphs, count, opt.seed ? opt.seed : 0x5eedull, base, st);
@@ -217,75 +280,59 @@ static gt_status ensure_lanes(gt_plan_st *plan) {
 // phase; the queue holds them level by level (all graphs' phases of one kind,
 // the largest graph first, before any phase of the next kind), so that the
 // items of a level find their graph's previous level finished or nearly so.
-static uint32_t clamp_items(int64_t x, int64_t hi) {
-  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(x, hi));
-}
-
-// The phases of one graph (at most kPersistMaxPhases), item counts from the
-// plan alone; with a descriptor L, also the ranges the first phase clears.
-int persist_phases(const GraphPlan &p, const StableLaunch *L, const gt_csc_t *out, int32_t g, bool validate,
-                   PersistPhase *ph) {
-  constexpr int64_t NT = kPersistThreads;
-  int k = 0;
-  auto add = [&](PersistKind kind, int64_t nitems) {
-    if (nitems <= 0) return;
-    PersistPhase &q = ph[k++];
-    q = PersistPhase{};
-    q.kind = kind;
-    q.graph = (uint32_t)g;
-    q.nitems = (uint32_t)nitems;
-    q.chunk = 1;
-  };
-  if (p.n == 0 || p.m == 0) {  // T = 0 everywhere
-    add(kPhFill, clamp_items((2 * (p.n + 1) + NT * 16 - 1) / (NT * 16), 64));
-    if (out) {
-      ph[k - 1].fill[0] = reinterpret_cast<uint32_t *>(out->offsets);
-      ph[k - 1].fill_words[0] = 2 * (uint64_t)(p.n + 1);
-    }
-    if (validate && p.n > 0) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
-    return k;
+// A device plan: the graphs' pointers and the queue order to the device,
+// then the planning kernel (layout, kernel arguments, phase table, ticket
+// table, queue size) and the persistent kernel.
+static gt_status enqueue_device_planned(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
+                                        hipStream_t st) {
+  const int32_t count = plan->count;
+  char *host = static_cast<char *>(plan->pk_host);
+  DevGraph *dg = reinterpret_cast<DevGraph *>(host);
+  uint32_t *order = reinterpret_cast<uint32_t *>(host + (plan->off_porder - plan->off_pgraph));
+  for (int32_t i = 0; i < count; ++i) {
+    DevGraph &g = dg[i];
+    g.n = graphs[i].n;
+    g.m = graphs[i].m;
+    g.offsets = graphs[i].offsets;
+    g.indices = graphs[i].indices;
+    g.payload = graphs[i].payload;
+    g.out_offsets = outs[i].offsets;
+    g.out_indices = outs[i].indices;
+    g.out_payload = outs[i].payload;
+    g.base = plan->graph_base[i];
+    order[i] = plan->order[i];
   }
-  const int64_t scan_tiles = (p.nbins + scan_tile_size() - 1) / scan_tile_size();
-  const int64_t status_words = p.passes > 1 ? p.ntiles * ((int64_t)1 << p.max_bits) : 0;
-  // counters and look-back words that start at zero
-  add(kPhFill, clamp_items((status_words + scan_tiles + 3 + NT * 16 - 1) / (NT * 16), 256));
-  if (L) {
-    ph[k - 1].fill[0] = L->status;
-    ph[k - 1].fill_words[0] = (uint64_t)status_words;
-    ph[k - 1].fill[1] = L->sstatus;
-    ph[k - 1].fill_words[1] = (uint64_t)scan_tiles;
-    ph[k - 1].fill[2] = L->f.total_items + 1;  // scan ticket, big- and huge-bin counts
-    ph[k - 1].fill_words[2] = 3;
-  }
-  if (validate) add(kPhValidate, clamp_items((p.n + NT - 1) / NT, 2048));
-  const int64_t nblk = tile_scan_blocks(p.ntiles);
-  add(kPhHist, std::min<int64_t>(kHistBlocks, std::max<int64_t>(1, p.ntiles)));
-  add(kPhTileBsum, nblk);
-  add(kPhTileBscan, (int64_t)1 << p.bits[0]);
-  add(kPhTileOff, nblk);
-  if (p.passes > 1) add(kPhDigitReduce, (int64_t)p.passes * (kMaxRadix / 64));
-  add(kPhDigitScan, p.passes);
-  add(kPhTileSrc, (p.ntiles + NT - 1) / NT);
-  add(kPhPass0, p.ntiles);
-  if (p.passes > 1) add(kPhPass1, p.ntiles);
-  add(kPhBinItems, (p.nbins + NT - 1) / NT);
-  add(kPhScan, scan_tiles);
-  add(kPhItemMap, (p.nbins + NT - 1) / NT);
-  add(kPhBigCount, p.max_items);
-  add(kPhBigScan, p.max_big);
-  add(kPhHugeScan, p.max_huge);
-  add(kPhFinal, p.max_items);
-  return k;
-}
-
-// Items per ticket: long phases hand out runs of up to 4 consecutive items
-// (fewer tickets and dependency checks), as long as every resident
-// workgroup still gets several tickets of the phase.  Look-back phases take
-// one item per ticket: a run's last tile would hold up the next run's first.
-static uint32_t persist_chunk(uint32_t kind, uint32_t nitems, int grid) {
-  if (kind == kPhPass1 || kind == kPhScan) return 1;
-  const int64_t c = (int64_t)nitems / (8 * (int64_t)std::max(grid, 1));
-  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>(c, 4));
+  const size_t copy = plan->off_porder + sizeof(uint32_t) * (size_t)count - plan->off_pgraph;
+  if (hipMemcpyAsync(ws + plan->off_pgraph, host, copy, hipMemcpyHostToDevice, st) != hipSuccess) return GT_ERR_HIP;
+  if (hipEventRecord(plan->pk_event, st) != hipSuccess) return GT_ERR_HIP;
+  plan->pk_pending = true;
+  // status word, ticket and the done counters of every phase there can be
+  if (launch_fill(reinterpret_cast<uint32_t *>(ws), persist_counters_end(count) / 4, 0u, st) != hipSuccess)
+    return GT_ERR_HIP;
+  DevPlanArgs d{};
+  d.graphs = reinterpret_cast<const DevGraph *>(ws + plan->off_pgraph);
+  d.order = reinterpret_cast<const uint32_t *>(ws + plan->off_porder);
+  d.choice = reinterpret_cast<const DevChoice *>(ws + plan->off_pchoice);
+  d.count = count;
+  d.validate = plan->validate;
+  d.grid = plan->pk_grid;
+  d.ws = ws;
+  d.desc = reinterpret_cast<StableLaunch *>(ws + plan->off_pdesc);
+  d.tmp = reinterpret_cast<PersistPhase *>(ws + plan->off_ptmp);
+  d.table = reinterpret_cast<PersistPhase *>(ws + plan->off_pphase);
+  d.tab = reinterpret_cast<uint32_t *>(ws + plan->off_ptab);
+  d.meta = reinterpret_cast<uint64_t *>(ws + plan->off_pmeta);
+  if (launch_persist_plan(d, st) != hipSuccess) return GT_ERR_HIP;
+  PersistArgs a{};
+  a.graphs = d.desc;
+  a.phases = d.table;
+  a.meta = d.meta;
+  a.tab = d.tab;
+  a.ticket = reinterpret_cast<unsigned long long *>(ws + 8);
+  a.done = reinterpret_cast<uint32_t *>(ws + kPersistDoneOff);
+  a.err = reinterpret_cast<uint32_t *>(ws);
+  if (launch_persistent(a, plan->pk_grid, st) != hipSuccess) return GT_ERR_HIP;
+  return GT_OK;
 }
 
 static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, const gt_csc_t *outs, char *ws,
@@ -297,6 +344,7 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
     if (hipEventSynchronize(plan->pk_event) != hipSuccess) return GT_ERR_HIP;
     plan->pk_pending = false;
   }
+  if (plan->device_plan) return enqueue_device_planned(plan, graphs, outs, ws, st);
   const int32_t count = plan->count;
   char *host = static_cast<char *>(plan->pk_host);
   StableLaunch *desc = reinterpret_cast<StableLaunch *>(host);
@@ -346,7 +394,10 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
     while (j + 1 < (uint64_t)nphases && table[j + 1].start <= t) ++j;
     tab[b] = (uint32_t)j;
   }
-  const size_t copy = (plan->off_ptab - plan->off_pdesc) + sizeof(uint32_t) * (size_t)ntab;
+  uint64_t *meta = reinterpret_cast<uint64_t *>(host + (plan->off_pmeta - plan->off_pdesc));
+  meta[0] = total;
+  meta[1] = (uint64_t)nphases;
+  const size_t copy = plan->off_pmeta + 2 * sizeof(uint64_t) - plan->off_pdesc;
   if (hipMemcpyAsync(ws + plan->off_pdesc, host, copy, hipMemcpyHostToDevice, st) != hipSuccess) return GT_ERR_HIP;
   if (hipEventRecord(plan->pk_event, st) != hipSuccess) return GT_ERR_HIP;
   plan->pk_pending = true;
@@ -357,8 +408,7 @@ static gt_status enqueue_persistent(gt_plan_st *plan, const gt_csr_t *graphs, co
   PersistArgs a{};
   a.graphs = reinterpret_cast<const StableLaunch *>(ws + plan->off_pdesc);
   a.phases = reinterpret_cast<const PersistPhase *>(ws + plan->off_pphase);
-  a.nphases = nphases;
-  a.total = total;
+  a.meta = reinterpret_cast<const uint64_t *>(ws + plan->off_pmeta);
   a.tab = reinterpret_cast<const uint32_t *>(ws + plan->off_ptab);
   a.ticket = reinterpret_cast<unsigned long long *>(ws + 8);
   a.done = reinterpret_cast<uint32_t *>(ws + kPersistDoneOff);
@@ -460,6 +510,7 @@ gt_status gt_autotune(const gt_csr_t *g, gt_csc_t *out, void *workspace, size_t 
 // (e.g. the autotuner's best); the plan's workspace size may grow.
 gt_status gt_plan_set_config(gt_plan_t plan, int32_t i, int32_t config) {
   if (plan == nullptr || i < 0 || i >= plan->count || config < 0 || config >= kMlpOut) return GT_ERR_INVALID_ARGUMENT;
+  if (plan->device_plan) return GT_ERR_UNSUPPORTED;  // the choice lives on the device
   GraphPlan &p = plan->graphs[i];
   const GraphPlan keep = p;
   config_params(config, &p.fine_bits, &p.digit_bits, &p.variant);

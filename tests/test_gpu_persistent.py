@@ -2,7 +2,9 @@
 drains a device work queue of every graph's phases, against the oracle:
 eager, with payloads, empty and single-pass graphs, offsets validation, the
 learned policy, back-to-back calls, replays of a captured HIP graph, and an
-invalid graph in a batch (reported, every write inside its outputs).
+invalid graph in a batch (reported, every write inside its outputs); and
+plans whose learned choice is made on the device (GT_FLAG_DEVICE_PLAN),
+eagerly and captured together with the transposition.
 Every case prints its name first."""
 import numpy as np
 import pytest
@@ -178,3 +180,70 @@ def test_persistent_invalid_ids_stay_in_bounds(hip_device, validate):
     assert bool((S_big[m:] == canary).all()), "write past S"
     assert bool((Q_big[m:] == canary).all()), "write past Q"
     check(outs[1:], [good])
+
+
+def device_plan_options(gt):
+    from paper_2501_06872_amd import mlp_model
+    return gt.make_options(policy=gt.POLICY_MLP, model_path=mlp_model.DEFAULT_PATH,
+                           flags=gt.FLAG_PERSISTENT | gt.FLAG_DEVICE_PLAN)
+
+
+def check_device_choices(plan, dev):
+    learned = 0
+    for i in range(len(dev)):
+        c = plan.device_choice(i)
+        assert c["variant"] == 1 and 4 <= c["digit_bits"] <= 9 and -1 <= c["config"] < 32, (i, c)
+        learned += c["config"] >= 0
+    return learned
+
+
+def test_device_plan_matches_oracle(hip_device):
+    """The learned choice made on the device (sampling, network, argmin in
+    kernels), every graph laid out and the queue built by the planning
+    kernel: outputs against the oracle."""
+    import paper_2501_06872_amd as gt
+    host = batch(16, seed=51, shift=4)
+    say(f"[case] device-planned persistent batch, {len(host)} graphs")
+    dev = [to_dev(*g, hip_device) for g in host]
+    plan = gt.Plan(dev, device_plan_options(gt))
+    outs = plan.run_batched(dev)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    check(outs, host)
+    learned = check_device_choices(plan, dev)
+    say(f"  {learned} of {len(dev)} graphs took the network's choice")
+    assert learned > 0
+    outs2 = plan.run_batched(dev)  # a second call: the same choices, laid out again
+    torch.cuda.synchronize()
+    check(outs2, host)
+
+
+def test_device_plan_and_transpose_in_one_captured_graph(hip_device):
+    """gt_plan (device plan) and gt_transpose_batched captured together in one
+    HIP graph, replayed three times with scribbled outputs between."""
+    import paper_2501_06872_amd as gt
+    host = batch(12, seed=53, shift=5)
+    say(f"[case] device plan + persistent batch captured together, {len(host)} graphs")
+    dev = [to_dev(*g, hip_device) for g in host]
+    outs = [(torch.empty(g[0].numel(), dtype=torch.int64, device=hip_device),
+             torch.empty(g[1].numel(), dtype=torch.int32, device=hip_device),
+             torch.empty(g[1].numel(), dtype=g[2].dtype, device=hip_device) if g[2] is not None else None)
+            for g in dev]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, capture_error_mode="relaxed"):
+        plan = gt.Plan(dev, device_plan_options(gt))
+        plan.run_batched(dev, outs)
+    for rep in range(3):
+        for T, S, Q in outs:
+            T.fill_(-7)
+            S.fill_(-7)
+            if Q is not None:
+                Q.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        assert plan.device_status() == 0
+        check(outs, host)
+    assert check_device_choices(plan, dev) > 0
