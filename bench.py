@@ -136,9 +136,11 @@ def measure_batch(steps, warmup, with_autotune=True, check=True):
     plan per graph, one stream) against one batched plan replayed from a
     captured HIP graph, with the parameters chosen three ways: the heuristic,
     the learned policy (MLP), and the autotuner's best configuration per
-    graph.  Returns a dict of times, speedups, plan times, the MLP's regret
-    against the autotuner, and output checks (plain against the oracle, every
-    batched variant against plain)."""
+    graph; the persistent kernel with the heuristic and learned choices; and
+    the learned plan made on the device, captured with the batch.  Returns a
+    dict of times, speedups, plan times, the MLP's regret against the
+    autotuner, and output checks (plain against the oracle, every batched
+    variant against plain)."""
     import concurrent.futures
     import torch
     import gen
@@ -269,6 +271,26 @@ def measure_batch(steps, warmup, with_autotune=True, check=True):
         res[f"batched_{name}_speedup"] = round(ms_plain / ms, 3)
         res[f"batched_{name}_identical_to_plain"] = bool(same)
         del hg
+    # planning inside the capture: the learned choice made on the device,
+    # every graph laid out by a planning kernel, the persistent kernel; the
+    # plan and the batch are captured together and replayed
+    hg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(hg, capture_error_mode="relaxed"):
+        p_dev = gt.Plan(graphs, gt.make_options(policy=gt.POLICY_MLP, model_path=model,
+                                                flags=gt.FLAG_PERSISTENT | gt.FLAG_DEVICE_PLAN), workspace=ws_b)
+        p_dev.run_batched(graphs, outs_b)
+    for T, S, Q in outs_b:
+        T.fill_(-7)
+        S.fill_(-7)
+    hg.replay()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and (a[2] is None or torch.equal(a[2], b[2]))
+               for a, b in zip(outs_p, outs_b))
+    ms = timed(hg.replay, steps)
+    res["planned_in_capture_persistent_mlp_ms"] = round(ms, 4)
+    res["planned_in_capture_persistent_mlp_speedup"] = round(ms_plain / ms, 3)
+    res["planned_in_capture_persistent_mlp_identical_to_plain"] = bool(same)
+    del hg, p_dev
     res["plan_s"] = {"plain_all_graphs": round(plan_plain_s, 4), "batched_heuristic": round(plan_heur_s, 4),
                      "batched_mlp": round(plan_mlp_s, 4), "persistent_heuristic": round(plan_pheur_s, 4),
                      "persistent_mlp": round(plan_pmlp_s, 4)}
