@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gt_device.hpp"
 #include "gt_internal.h"
 
@@ -900,11 +902,15 @@ __device__ __forceinline__ void big_scan_body(const FinalArgs &a, int64_t item, 
 template <int WAVES, int ITEMS, int FBITS>
 struct FinalShared {
   static constexpr int NT = WAVES * kWave, TILE = NT * ITEMS, FW = 1 << FBITS;
-  static constexpr int STAGE_WORDS = TILE > 2 * WAVES * FW ? TILE : 2 * WAVES * FW;
+  // The per-wave lane-mask tables and counters hold one key more (FW): the
+  // lanes of the item's partial row past its last edge rank under it, so no
+  // row is ranked under a lane predicate.  Rows padded to 16 bytes.
+  static constexpr int FWX = FW + 8;
+  static constexpr int STAGE_WORDS = TILE > 2 * WAVES * FWX ? TILE : 2 * WAVES * FWX;
   alignas(16) uint32_t stage[STAGE_WORDS];
-  alignas(16) uint16_t wcnt[WAVES][FW];
+  alignas(16) uint16_t wcnt[WAVES][FWX];
   uint32_t tot[FW];
-  uint32_t toff[FW];
+  uint32_t toff[FW + 1];
   uint64_t cur[FW];
   uint32_t w32[NT / kWave + 1];
 };
@@ -912,57 +918,69 @@ template <int WAVES, int ITEMS, int FBITS, bool PAY>
 __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, FinalShared<WAVES, ITEMS, FBITS> &sh) {
   using Sh = FinalShared<WAVES, ITEMS, FBITS>;
   constexpr int NT = Sh::NT;
-  constexpr int TILE = Sh::TILE;
   constexpr int FW = Sh::FW;
+  constexpr int FWX = Sh::FWX;
   uint32_t(&s_stage)[Sh::STAGE_WORDS] = sh.stage;
-  uint16_t(&s_wcnt)[WAVES][FW] = sh.wcnt;
+  uint16_t(&s_wcnt)[WAVES][FWX] = sh.wcnt;
   uint32_t(&s_tot)[FW] = sh.tot;
-  uint32_t(&s_toff)[FW] = sh.toff;
+  uint32_t(&s_toff)[FW + 1] = sh.toff;
   uint64_t(&s_cur)[FW] = sh.cur;
   uint32_t(&s_w32)[NT / kWave + 1] = sh.w32;
   const uint32_t total = *a.total_items;
   const uint4 dsc = a.item_desc[item];  // grid = the most items a plan can have
   if (item >= (int64_t)total) return;
-  const int tid = GT_TID(), lane = tid & (kWave - 1), w = tid / kWave;
-  const uint32_t f = dsc.z;
-  const bool whole = (dsc.w >> 31) != 0u;
+  const int tid = GT_TID(), lane = tid & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  // the item's descriptor is the workgroup's: scalar registers, so the tile's
+  // base pointers are scalar and every access below takes a 32-bit offset
+  const uint32_t dx = (uint32_t)__builtin_amdgcn_readfirstlane((int)dsc.x);
+  const uint32_t dy = (uint32_t)__builtin_amdgcn_readfirstlane((int)dsc.y);
+  const uint32_t f = (uint32_t)__builtin_amdgcn_readfirstlane((int)dsc.z);
+  const uint32_t dw = (uint32_t)__builtin_amdgcn_readfirstlane((int)dsc.w);
+  const bool whole = (dw >> 31) != 0u;
   const int fw = 1 << a.fine_bits;
   const uint32_t vmask = (uint32_t)fw - 1u;
-  const uint64_t cb = (uint64_t)dsc.x | ((uint64_t)dsc.y << 32);
+  const uint64_t cb = (uint64_t)dx | ((uint64_t)dy << 32);
   const uint64_t bs = cb;  // a whole bin starts at its item's first edge
-  const int cnt = (int)(dsc.w & 0x7FFFFFFFu);
+  const int cnt = (int)(dw & 0x7FFFFFFFu);
   const int64_t v0 = (int64_t)f << a.fine_bits;
   auto row_idx = [&](int j) { return (w * ITEMS + j) * kWave + lane; };
 
-  lds_zero16(&s_wcnt[0][0], WAVES * FW * 2, tid, NT);
-  lds_zero16(s_stage, 2 * WAVES * FW * 4, tid, NT);
+  lds_zero16(&s_wcnt[0][0], WAVES * FWX * 2, tid, NT);
+  lds_zero16(s_stage, 2 * WAVES * FWX * 4, tid, NT);
   if (!whole) {
     const uint32_t *row = a.cntab + (uint64_t)item * fw;
     for (int v = tid; v < fw; v += NT) s_cur[v] = v0 + v < a.n ? (uint64_t)a.T[v0 + v] + row[v] : 0ull;
   }
   __syncthreads();
-  uint32_t key[ITEMS], lpos[ITEMS];
   // keys and sources at once (the sources are staged later; the payload is
   // loaded when it is staged, which keeps three workgroups per CU).  The key
   // loads take a clamped index and no branch: a 16-bit load masked inside a
   // per-row branch is waited for before the next one is issued.
-  uint32_t src[ITEMS];
+  const uint16_t *kin = a.in_key + cb;
+  const int32_t *sin = a.in_src + cb;
+  uint32_t key[ITEMS], src[ITEMS], lpos[ITEMS];
   if (cnt > 0) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) key[j] = a.in_key[cb + (row_idx(j) < cnt ? row_idx(j) : cnt - 1)];
+    for (int j = 0; j < ITEMS; ++j) key[j] = kin[row_idx(j) < cnt ? row_idx(j) : cnt - 1];
   }
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)a.in_src[cb + row_idx(j)] : 0u;
+  for (int j = 0; j < ITEMS; ++j) src[j] = row_idx(j) < cnt ? (uint32_t)sin[row_idx(j)] : 0u;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? key[j] & vmask : 0u;
+  for (int j = 0; j < ITEMS; ++j) key[j] = row_idx(j) < cnt ? key[j] & vmask : (uint32_t)FW;
   {
-    unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FW;
+    unsigned long long *tab = reinterpret_cast<unsigned long long *>(s_stage) + w * FWX;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      if ((w * ITEMS + j) * kWave >= cnt) break;  // the rest of this wave's rows hold no edge
-      lpos[j] = rank_row_lds(key[j], row_idx(j) < cnt, s_wcnt[w], tab, lane);
+      lpos[j] = 0u;
+      if ((w * ITEMS + j) * kWave < cnt)  // rows past the last edge hold none
+        lpos[j] = rank_row_lds(key[j], true, s_wcnt[w], tab, lane);
     }
   }
+  // the keys' LDS addresses are recomputed below instead of being kept live
+  // across the scans (one register per row instead of two)
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) asm volatile("" : "+v"(key[j]));
   __syncthreads();
   for (int v = tid; v < fw; v += NT) {
     uint32_t run = 0;
@@ -975,6 +993,10 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
     s_tot[v] = run;
     s_toff[v] = run;
   }
+  // the extra key FW sorts after every edge: its lanes (the partial row's,
+  // all in one wave) land on slots cnt, cnt + 1, ..., i.e. on their own
+  if (tid < WAVES) s_wcnt[tid][FW] = 0;
+  if (tid == 0) s_toff[FW] = (uint32_t)cnt;
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, fw, s_w32);
   // A whole bin: its counts are the in-degrees of its vertices, and its
@@ -988,10 +1010,19 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
     }
   }
   if (cnt == 0) return;
-  // the local sorted position of every edge of this thread
+  // The local sorted position of every edge of this thread, in batches of G
+  // rows (the reads of a batch share one wait; the scheduling barrier keeps
+  // the compiler from hoisting every batch's reads at once).  Rows past the
+  // last edge were not ranked and are neither placed nor staged.
+  constexpr int G = 4;
+  const int nrows = (cnt + kWave - 1) / kWave;  // ranked rows of the item
+  auto ranked = [&](int j) { return w * ITEMS + j < nrows; };
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (row_idx(j) < cnt) lpos[j] += s_toff[key[j]] + s_wcnt[w][key[j]];
+  for (int j0 = 0; j0 < ITEMS; j0 += G) {
+#pragma unroll
+    for (int j = j0; j < j0 + G; ++j) lpos[j] += s_toff[key[j]] + s_wcnt[w][key[j]];
+    __builtin_amdgcn_sched_barrier(0);
+  }
   uint32_t vpk[(ITEMS + 1) / 2];
 #pragma unroll
   for (int k = 0; k < (ITEMS + 1) / 2; ++k) vpk[k] = 0u;
@@ -999,54 +1030,66 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
     // the vertex of every sorted slot (for its cursor)
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos[j]] = key[j];
+      if (ranked(j)) s_stage[lpos[j]] = key[j] & vmask;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const int i = k * NT + tid;
-      if (i < cnt) vpk[k >> 1] |= s_stage[i] << ((k & 1) * 16);
-    }
+    for (int k = 0; k < ITEMS; ++k) vpk[k >> 1] |= (s_stage[k * NT + tid] & vmask) << ((k & 1) * 16);
   }
-  auto gpos_of = [&](int k, int i) -> uint64_t {
-    if (whole) return bs + (uint64_t)i;
-    const uint32_t v = (vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
-    return s_cur[v] + (uint64_t)i;
-  };
   // Only an invalid graph has a destination v >= n (in the last bin, below
   // the next power of two).  A whole bin keeps such edges inside its own
   // slots; in a chunk of a big bin they have no cursor (T[v] does not exist)
   // and are dropped, so no write leaves [0, m).  k_hist has already flagged
   // the graph as invalid.
   const int64_t nvalid = a.n - v0;  // vertices of the bin that exist
-  auto slot_ok = [&](int k, int i) -> bool {
-    if (i >= cnt) return false;
-    if (whole) return true;
-    return (int64_t)((vpk[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu) < nvalid;
+  // staged slot k * NT + tid of every row -> out (sources, then payload)
+  auto place = [&](auto *out, const uint32_t(&val)[ITEMS]) {
+    using E = typename std::remove_pointer<decltype(out)>::type;
+    if (whole) {
+      E *ob = out + bs;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        if (k * NT + tid < cnt) ob[k * NT + tid] = (E)val[k];
+    } else {
+#pragma unroll
+      for (int k0 = 0; k0 < ITEMS; k0 += G) {
+        uint64_t c[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) c[k] = s_cur[(vpk[(k0 + k) >> 1] >> (((k0 + k) & 1) * 16)) & 0xFFFFu];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          const int i = (k0 + k) * NT + tid;
+          const uint32_t v = (vpk[(k0 + k) >> 1] >> (((k0 + k) & 1) * 16)) & 0xFFFFu;
+          if (i < cnt && (int64_t)v < nvalid) out[c[k] + (uint64_t)i] = (E)val[k0 + k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
   };
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j)
-    if (row_idx(j) < cnt) s_stage[lpos[j]] = src[j];
+    if (ranked(j)) s_stage[lpos[j]] = src[j];
   __syncthreads();
+  {
+    uint32_t val[ITEMS];
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int i = k * NT + tid;
-    if (slot_ok(k, i)) a.S[gpos_of(k, i)] = (int32_t)s_stage[i];
+    for (int k = 0; k < ITEMS; ++k) val[k] = s_stage[k * NT + tid];
+    place(a.S, val);
   }
   if (PAY) {
+    const uint32_t *pin = a.in_pay + cb;
     uint32_t pay[ITEMS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) pay[j] = row_idx(j) < cnt ? a.in_pay[cb + row_idx(j)] : 0u;
+    for (int j = 0; j < ITEMS; ++j) pay[j] = row_idx(j) < cnt ? pin[row_idx(j)] : 0u;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
-      if (row_idx(j) < cnt) s_stage[lpos[j]] = pay[j];
+      if (ranked(j)) s_stage[lpos[j]] = pay[j];
     __syncthreads();
+    uint32_t val[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const int i = k * NT + tid;
-      if (slot_ok(k, i)) a.Q[gpos_of(k, i)] = s_stage[i];
-    }
+    for (int k = 0; k < ITEMS; ++k) val[k] = s_stage[k * NT + tid];
+    place(a.Q, val);
   }
 }
 
