@@ -301,13 +301,23 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   GT_TIMED("k_tile_src", launch_tile_src(L.O, L.n, L.m, L.tile, L.ntiles, L.tsrc, st));
   for (int pass = 0; pass < L.passes; ++pass) {
     const bool first = pass == 0, last = pass == L.passes - 1;
-    if (!first) {  // the first pass places its tiles with k_hist's tile offsets
-      GT_TIMED("k_fill_status", launch_fill(L.status, L.status_words, 0u, st));
-      GT_CHK(launch_fill(L.ticket + pass, 1, 0u, st));
+    LsdArgs a = L.lsd[pass];
+    if (!first) {
+      // The first pass places its tiles with k_hist's tile counts.  A later
+      // pass counts its digit per tile over its input (the previous pass's
+      // keys) and places its tiles with their column prefix too, instead of
+      // a look-back (the persistent kernel keeps the look-back).  The tile
+      // buffers are the first pass's (a later digit is never wider).
+      const int radix = 1 << p.bits[pass];
+      const void *keys = L.pk[pass] ? static_cast<const void *>(a.in_key16) : static_cast<const void *>(a.in_key);
+      GT_TIMED("k_tile_hist", launch_tile_hist(keys, L.pk[pass], L.m, a.shift, radix, L.tile, L.ntiles, L.tcnt, st));
+      GT_TIMED("k_tile_scan", launch_tile_scan(L.tcnt, L.ntiles, radix, L.tbsum, L.dtot + pass * kMaxRadix, L.toff,
+                                               st));
+      a.tile_off = L.toff;
+      a.placed = 1;
     }
     static const char *kLsdNames[kMaxPasses] = {"k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2"};
-    GT_TIMED(kLsdNames[pass], launch_lsd(L.variant, p.bits[pass], L.lsd[pass], first, L.pay, last, L.pk[pass], L.wide,
-                                         st));
+    GT_TIMED(kLsdNames[pass], launch_lsd(L.variant, p.bits[pass], a, first, L.pay, last, L.pk[pass], L.wide, st));
   }
   const FinalArgs &f = L.f;
   GT_TIMED("k_bin_items", launch_bin_items(f, st));

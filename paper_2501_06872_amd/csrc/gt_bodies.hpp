@@ -263,6 +263,75 @@ __device__ __forceinline__ void tile_off_body(const uint16_t *__restrict__ tilec
     }
   }
 }
+// Per-tile digit counts of a later pass, over the previous pass's output
+// (tile t = positions [t*TILE, (t+1)*TILE) of its keys): one row of 16-bit
+// counts per tile, as k_hist writes for the first pass, so that the pass
+// places its tiles with their column prefix instead of a look-back.  Each
+// thread reads a contiguous stretch of keys and adds runs of equal digits
+// with one LDS atomic (a skewed graph's intermediate holds long runs of one
+// destination), into an LDS histogram of its wave.
+template <int NT>
+struct TileHistShared {
+  uint32_t c[NT / kWave][kMaxRadix];
+};
+template <int NT, int TILE, typename K>
+__device__ __forceinline__ void tile_hist_body(const K *__restrict__ keys, int64_t m, int shift, int radix,
+                                               uint16_t *__restrict__ tilecnt, int64_t t, TileHistShared<NT> &sh) {
+  constexpr int NW = NT / kWave;
+  constexpr int PER = 16 / (int)sizeof(K);  // keys per 16-byte load
+  constexpr int V = TILE / PER / NT;        // loads per thread
+  static_assert(TILE % (PER * NT) == 0, "tile of whole 16-byte rows");
+  const int tid = GT_TID(), w = tid / kWave;
+  const uint32_t mask = (uint32_t)radix - 1u;
+  const int64_t base = t * TILE;
+  uint4 q[V];
+  const bool whole = base + TILE <= m;
+  if (whole) {
+    const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + base) + (int64_t)tid * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) q[v] = k4[v];
+  }
+  const int rbits = __builtin_ctz((unsigned)radix);
+  for (int i = tid; i < NW * radix; i += NT) sh.c[i >> rbits][i & (radix - 1)] = 0u;
+  __syncthreads();
+  uint32_t *c = sh.c[w];
+  if (whole) {
+    uint32_t prev = 0xFFFFFFFFu, run = 0;
+    auto add = [&](uint32_t key) {
+      const uint32_t d = (key >> shift) & mask;
+      if (d != prev) {
+        if (run) atomicAdd(&c[prev], run);
+        prev = d;
+        run = 0;
+      }
+      ++run;
+    };
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const uint32_t wd[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if constexpr (sizeof(K) == 2) {
+          add(wd[k] & 0xFFFFu);
+          add(wd[k] >> 16);
+        } else {
+          add(wd[k]);
+        }
+      }
+    }
+    atomicAdd(&c[prev], run);
+  } else {  // the last, ragged tile
+    for (int64_t e = base + tid; e < m; e += NT) atomicAdd(&c[((uint32_t)keys[e] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  uint16_t *row = tilecnt + t * radix;
+  for (int d = tid; d < radix; d += NT) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) sum += sh.c[x][d];
+    row[d] = (uint16_t)sum;
+  }
+}
 // Step 2 (digit level), part 1: sum the per-workgroup partial histograms of
 // the later passes.  Item (pass, 64-digit group); NT / 64 thread groups
 // split the partials.
@@ -379,11 +448,14 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
 
   lds_zero16(&s_wcnt[0][0], WAVES * RADIX * 2, tid, NT);
   lds_zero16(s_stage, 2 * WAVES * RADIX * 4, tid, NT);
-  // first pass: runs of consecutive tiles per XCD (their digit runs meet in
-  // one L2); later passes: tiles in ticket order, for the look-back
+  // A pass placed with per-tile digit offsets (the first pass always; a
+  // later pass when a.placed) takes its tiles in runs of consecutive tiles
+  // per XCD (their digit runs meet in one L2); a later pass with a look-back
+  // takes them in ticket order.
+  const bool placed = CSR_IN || a.placed;
   if (tid == 0)
     s_tile = order_in >= 0 ? order_in
-                           : (CSR_IN ? xcd_item(blockIdx.x, (a.m + TILE - 1) / TILE, GT_XCD_BLOCK)
+                           : (placed ? xcd_item(blockIdx.x, (a.m + TILE - 1) / TILE, GT_XCD_BLOCK)
                                      : (int64_t)atomicAdd(a.ticket, 1u));
   if (PK_IN && tid < 3) s_fl[tid] = 0;
   __syncthreads();
@@ -391,8 +463,9 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   // sources of a natural-order graph thin out towards high IDs, and a tile
   // there fills its sources from up to ~10^5 offsets, so those tiles start
   // first instead of closing the launch.  It places its tiles with the
-  // per-tile digit offsets of k_hist (no look-back); later passes take their
-  // tiles from a ticket and run a decoupled look-back over them.
+  // per-tile digit offsets of k_hist (no look-back); a later pass either
+  // places them with the offsets of k_tile_hist's counts or takes them from
+  // a ticket and runs a decoupled look-back over them.
   const int64_t ntiles = (a.m + TILE - 1) / TILE;
   const int64_t order = s_tile;  // position in the look-back chain
   const int64_t tile = CSR_IN ? ntiles - 1 - order : order;
@@ -460,19 +533,25 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   for (int d = tid; d < radix; d += NT) {
     uint32_t run = 0;
 #pragma unroll
-    for (int x = 0; x < WAVES; ++x) {
-      const uint32_t c = s_wcnt[x][d];
-      s_wcnt[x][d] = (uint16_t)run;
-      run += c;
-    }
+    for (int x = 0; x < WAVES; ++x) run += s_wcnt[x][d];
     s_tot[d] = run;
     s_toff[d] = run;
-    if constexpr (!CSR_IN) lookback_publish<SW>(static_cast<SW *>(a.status), order, radix, d, run);
+    if (!placed) lookback_publish<SW>(static_cast<SW *>(a.status), order, radix, d, run);
   }
   // the scan below reads s_toff in blocks of radix / NT entries per thread,
   // so with more digits than threads it reads other threads' writes
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, radix, s_misc);  // tile-local digit offsets (ends with a barrier)
+  for (int d = tid; d < radix; d += NT) {
+    uint32_t run = s_toff[d];
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      const uint32_t c = s_wcnt[x][d];
+      s_wcnt[x][d] = (uint16_t)run;
+      run += c;
+    }
+  }
+  __syncthreads();
   // first pass (no look-back wait below to bound the scheduler): the row
   // addresses of the ranking are recomputed from here on rather than kept
   // in registers across the scan, which keeps six waves per SIMD
@@ -488,7 +567,7 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   for (int j = 0; j < ITEMS; ++j) {
     if (row_idx(j) < cnt) {
       const uint32_t d = (key[j] >> a.shift) & dmask;
-      const uint32_t p = lpos.get(j) + s_toff[d] + s_wcnt[w][d];
+      const uint32_t p = lpos.get(j) + s_wcnt[w][d];
       lpos.set(j, p);
       s_stage[p] = key[j];
     }
@@ -519,11 +598,11 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
     const int64_t u = u0 + 1 + tid;
     o_first = u < a.n ? a.O[u] : a.m;
   }
-  // the tile's place within each digit (first pass: the column prefix of
-  // k_hist's tile counts; later passes: look-back across tiles); staged
-  // slot i of digit d goes to s_gbase[d] + i
+  // the tile's place within each digit (the column prefix of the per-tile
+  // counts, or the look-back across tiles); staged slot i of digit d goes
+  // to s_gbase[d] + i
   for (int d = tid; d < radix; d += NT) {
-    if constexpr (CSR_IN) {
+    if (placed) {
       s_gbase[d] = a.digit_start[d] + a.tile_off[tile * radix + d] - s_toff[d];
     } else {
       const uint64_t excl = lookback_wait<SW>(static_cast<SW *>(a.status), order, radix, d, s_tot[d]);
@@ -908,9 +987,10 @@ struct FinalShared {
   static constexpr int FWX = FW + 8;
   static constexpr int STAGE_WORDS = TILE > 2 * WAVES * FWX ? TILE : 2 * WAVES * FWX;
   alignas(16) uint32_t stage[STAGE_WORDS];
+  // per wave and vertex: the wave's count, then the slot of the wave's first
+  // edge of that vertex (the vertex's offset plus the earlier waves' counts)
   alignas(16) uint16_t wcnt[WAVES][FWX];
-  uint32_t tot[FW];
-  uint32_t toff[FW + 1];
+  uint32_t toff[FW];
   uint64_t cur[FW];
   uint32_t w32[NT / kWave + 1];
 };
@@ -922,8 +1002,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
   constexpr int FWX = Sh::FWX;
   uint32_t(&s_stage)[Sh::STAGE_WORDS] = sh.stage;
   uint16_t(&s_wcnt)[WAVES][FWX] = sh.wcnt;
-  uint32_t(&s_tot)[FW] = sh.tot;
-  uint32_t(&s_toff)[FW + 1] = sh.toff;
+  uint32_t(&s_toff)[FW] = sh.toff;
   uint64_t(&s_cur)[FW] = sh.cur;
   uint32_t(&s_w32)[NT / kWave + 1] = sh.w32;
   const uint32_t total = *a.total_items;
@@ -982,34 +1061,44 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) asm volatile("" : "+v"(key[j]));
   __syncthreads();
-  for (int v = tid; v < fw; v += NT) {
-    uint32_t run = 0;
+  // One vertex per thread (FW <= NT): the waves' counts stay in registers
+  // across the scan of the vertex totals, then each wave's entry becomes the
+  // slot of its first edge of the vertex.
+  static_assert(FW <= NT, "one vertex per thread");
+  uint32_t wc[WAVES];
+  if (tid < fw) {
+    uint32_t t = 0;
 #pragma unroll
     for (int x = 0; x < WAVES; ++x) {
-      const uint32_t c = s_wcnt[x][v];
-      s_wcnt[x][v] = (uint16_t)run;
-      run += c;
+      wc[x] = s_wcnt[x][tid];
+      t += wc[x];
     }
-    s_tot[v] = run;
-    s_toff[v] = run;
+    s_toff[tid] = t;
   }
   // the extra key FW sorts after every edge: its lanes (the partial row's,
   // all in one wave) land on slots cnt, cnt + 1, ..., i.e. on their own
-  if (tid < WAVES) s_wcnt[tid][FW] = 0;
-  if (tid == 0) s_toff[FW] = (uint32_t)cnt;
+  if (tid < WAVES) s_wcnt[tid][FW] = (uint16_t)cnt;
   __syncthreads();
   block_excl_scan<NT, uint32_t>(s_toff, fw, s_w32);
   // A whole bin: its counts are the in-degrees of its vertices, and its
   // staged order is its final CSC order, so staged slot i goes to bs + i.
   // A chunk of a big bin: slot i of vertex v goes to s_cur[v] + i.
-  for (int v = tid; v < fw; v += NT) {
+  if (tid < fw) {
+    const uint32_t off = s_toff[tid];
+    uint32_t run = off;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      s_wcnt[x][tid] = (uint16_t)run;
+      run += wc[x];
+    }
     if (whole) {
-      if (v0 + v < a.n) a.T[v0 + v] = (int64_t)(bs + s_toff[v]);
+      if (v0 + tid < a.n) a.T[v0 + tid] = (int64_t)(bs + off);
     } else {
-      s_cur[v] -= s_toff[v];
+      s_cur[tid] -= off;
     }
   }
   if (cnt == 0) return;
+  __syncthreads();
   // The local sorted position of every edge of this thread, in batches of G
   // rows (the reads of a batch share one wait; the scheduling barrier keeps
   // the compiler from hoisting every batch's reads at once).  Rows past the
@@ -1020,7 +1109,7 @@ __device__ __forceinline__ void final_body(const FinalArgs &a, int64_t item, Fin
 #pragma unroll
   for (int j0 = 0; j0 < ITEMS; j0 += G) {
 #pragma unroll
-    for (int j = j0; j < j0 + G; ++j) lpos[j] += s_toff[key[j]] + s_wcnt[w][key[j]];
+    for (int j = j0; j < j0 + G; ++j) lpos[j] += s_wcnt[w][key[j]];
     __builtin_amdgcn_sched_barrier(0);
   }
   uint32_t vpk[(ITEMS + 1) / 2];

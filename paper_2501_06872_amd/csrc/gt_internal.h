@@ -34,7 +34,10 @@ struct LsdArgs {
   const int32_t *D;
   const uint32_t *P;
   const int32_t *tile_src0;
-  const uint32_t *tile_off;  // first pass: [ntiles][radix] offset of each tile within each digit
+  // [ntiles][radix] offset of each tile within each digit: the first pass,
+  // and a later pass when `placed` (else it runs a look-back)
+  const uint32_t *tile_off;
+  int placed;
   // partitioned input (later passes)
   const int32_t *in_src;
   const uint32_t *in_key;
@@ -241,6 +244,11 @@ constexpr int kTileBlk = 64;  // tiles per block of the first pass's tile prefix
 __host__ __device__ inline int64_t tile_scan_blocks(int64_t ntiles) { return (ntiles + kTileBlk - 1) / kTileBlk; }
 hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, uint32_t *bsum, uint64_t *totals0,
                             uint32_t *tileoff, hipStream_t st);
+// Per-tile 16-bit counts (tilecnt[ntiles][radix]) of the digit (key >> shift)
+// & (radix - 1) over the keys of a later pass's input (16-bit packed keys
+// when key16, else 32-bit keys), in that pass's tiles of `tile` edges.
+hipError_t launch_tile_hist(const void *keys, bool key16, int64_t m, int shift, int radix, int64_t tile,
+                            int64_t ntiles, uint16_t *tilecnt, hipStream_t st);
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
                              uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
                              uint32_t *err, hipStream_t st);

@@ -82,6 +82,13 @@ __global__ __launch_bounds__(256) void k_tile_off(const uint16_t *__restrict__ t
   tile_off_body<256>(tilecnt, ntiles, radix, nblk, bpre, tileoff, blockIdx.x);
 }
 
+template <int TILE, typename K>
+__global__ __launch_bounds__(256) void k_tile_hist(const K *__restrict__ keys, int64_t m, int shift, int radix,
+                                                   uint16_t *__restrict__ tilecnt) {
+  __shared__ TileHistShared<256> sh;
+  tile_hist_body<256, TILE, K>(keys, m, shift, radix, tilecnt, blockIdx.x, sh);
+}
+
 __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict__ part, int nblocks, HistArgs h,
                                                       uint64_t *totals) {
   __shared__ ReduceShared<256> sh;
@@ -304,6 +311,27 @@ hipError_t launch_tile_scan(const uint16_t *tilecnt, int64_t ntiles, int radix, 
   hipLaunchKernelGGL(k_tile_bscan, dim3((unsigned)radix), dim3(256), 0, st, bsum, nblk, totals0);
   hipLaunchKernelGGL(k_tile_off, dim3((unsigned)nblk), dim3(256), 0, st, tilecnt, ntiles, radix, nblk, bsum, tileoff);
   return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t launch_tile_hist_k(const K *keys, int64_t m, int shift, int radix, int64_t tile, int64_t ntiles,
+                                     uint16_t *tilecnt, hipStream_t st) {
+  const dim3 grid((unsigned)ntiles), blk(256);
+  switch (tile) {
+    case 4096: hipLaunchKernelGGL((k_tile_hist<4096, K>), grid, blk, 0, st, keys, m, shift, radix, tilecnt); break;
+    case 8192: hipLaunchKernelGGL((k_tile_hist<8192, K>), grid, blk, 0, st, keys, m, shift, radix, tilecnt); break;
+    case 16384: hipLaunchKernelGGL((k_tile_hist<16384, K>), grid, blk, 0, st, keys, m, shift, radix, tilecnt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_hist(const void *keys, bool key16, int64_t m, int shift, int radix, int64_t tile,
+                            int64_t ntiles, uint16_t *tilecnt, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (radix < 1 || radix > kMaxRadix || ntiles != (m + tile - 1) / tile) return hipErrorInvalidValue;
+  return key16 ? launch_tile_hist_k(static_cast<const uint16_t *>(keys), m, shift, radix, tile, ntiles, tilecnt, st)
+               : launch_tile_hist_k(static_cast<const uint32_t *>(keys), m, shift, radix, tile, ntiles, tilecnt, st);
 }
 
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
