@@ -294,9 +294,13 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
   if (p.strategy != GT_STRATEGY_STABLE) return enqueue_unordered(p, g, out, ws, prof, st);
 
   const StableLaunch L = stable_launch(p, g, out, ws, validate);
-  GT_TIMED("k_hist", launch_hist(L.D, L.m, L.n, L.h, L.tile, L.ntiles, L.hist_blocks, L.part, L.tcnt, L.err, st));
+  // k_hist counts the first pass's digit only: every later pass counts its
+  // own per tile (below), and its digit totals come from those counts
+  HistArgs h0 = L.h;
+  h0.passes = 1;
+  GT_TIMED("k_hist", launch_hist(L.D, L.m, L.n, h0, L.tile, L.ntiles, L.hist_blocks, L.part, L.tcnt, L.err, st));
   GT_TIMED("k_tile_scan", launch_tile_scan(L.tcnt, L.ntiles, L.radix0, L.tbsum, L.dtot, L.toff, st));
-  GT_TIMED("k_digit_scan", launch_digit_scan(L.part, L.hist_blocks, L.h, L.dtot, L.digit, L.bins, L.nbins_total,
+  GT_TIMED("k_digit_scan", launch_digit_scan(L.part, L.hist_blocks, h0, L.dtot, L.digit, L.bins, L.nbins_total,
                                              L.m, L.err, st));
   GT_TIMED("k_tile_src", launch_tile_src(L.O, L.n, L.m, L.tile, L.ntiles, L.tsrc, st));
   for (int pass = 0; pass < L.passes; ++pass) {
@@ -313,6 +317,8 @@ gt_status enqueue_graph(const GraphPlan &p, const gt_csr_t &g, const gt_csc_t &o
       GT_TIMED("k_tile_hist", launch_tile_hist(keys, L.pk[pass], L.m, a.shift, radix, L.tile, L.ntiles, L.tcnt, st));
       GT_TIMED("k_tile_scan", launch_tile_scan(L.tcnt, L.ntiles, radix, L.tbsum, L.dtot + pass * kMaxRadix, L.toff,
                                                st));
+      GT_TIMED("k_digit_scan", launch_digit_scan_pass(L.dtot, L.h, pass, L.digit, L.bins, L.nbins_total, L.m, L.err,
+                                                      st));
       a.tile_off = L.toff;
       a.placed = 1;
     }

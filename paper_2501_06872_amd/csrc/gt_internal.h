@@ -252,5 +252,9 @@ hipError_t launch_tile_hist(const void *keys, bool key16, int64_t m, int shift, 
 hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &h, uint64_t *totals,
                              uint64_t *digit_start, uint64_t *bin_start, int64_t nbins_total, int64_t m,
                              uint32_t *err, hipStream_t st);
+// The digit starts of one pass from its totals (totals[pass][radix]).
+hipError_t launch_digit_scan_pass(const uint64_t *totals, const HistArgs &h, int pass, uint64_t *digit_start,
+                                  uint64_t *bin_start, int64_t nbins_total, int64_t m, uint32_t *err,
+                                  hipStream_t st);
 
 }  // namespace gt

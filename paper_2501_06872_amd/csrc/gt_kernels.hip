@@ -95,11 +95,12 @@ __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t *__restrict
   digit_reduce_body<256>(part, nblocks, h, totals, blockIdx.x, sh);
 }
 
+// workgroup i scans pass p0 + i
 __global__ __launch_bounds__(1024) void k_digit_scan(const uint64_t *__restrict__ totals, HistArgs h,
                                                      uint64_t *digit_start, uint64_t *bin_start,
-                                                     int64_t nbins_total, int64_t m, uint32_t *err) {
+                                                     int64_t nbins_total, int64_t m, uint32_t *err, int p0) {
   __shared__ DigitScanShared<1024> sh;
-  digit_scan_body<1024>(totals, h, digit_start, bin_start, nbins_total, m, err, blockIdx.x, sh);
+  digit_scan_body<1024>(totals, h, digit_start, bin_start, nbins_total, m, err, p0 + (int)blockIdx.x, sh);
 }
 
 template <int WAVES, int ITEMS, int RBITS, bool CSR_IN, bool PAY, bool LAST, bool PACKED, typename SW>
@@ -339,7 +340,16 @@ hipError_t launch_digit_scan(const uint32_t *part, int nblocks, const HistArgs &
                              uint32_t *err, hipStream_t st) {
   hipLaunchKernelGGL(k_digit_reduce, dim3(h.passes * (kMaxRadix / 64)), dim3(256), 0, st, part, nblocks, h, totals);
   hipLaunchKernelGGL(k_digit_scan, dim3(h.passes), dim3(1024), 0, st, totals, h, digit_start, bin_start,
-                     nbins_total, m, err);
+                     nbins_total, m, err, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_digit_scan_pass(const uint64_t *totals, const HistArgs &h, int pass, uint64_t *digit_start,
+                                  uint64_t *bin_start, int64_t nbins_total, int64_t m, uint32_t *err,
+                                  hipStream_t st) {
+  if (pass < 0 || pass >= h.passes) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_digit_scan, dim3(1), dim3(1024), 0, st, totals, h, digit_start, bin_start, nbins_total, m,
+                     err, pass);
   return hipGetLastError();
 }
 
