@@ -147,7 +147,7 @@ __device__ T block_excl_scan(T *s, int len, T *wsum) {
 // blocks round-robin over the XCDs; the item count's tail beyond whole
 // rounds keeps the identity map.  A bijection on [0, count).
 #ifndef GT_XCD_BLOCK
-#define GT_XCD_BLOCK 16
+#define GT_XCD_BLOCK 64
 #endif
 constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_item(int64_t i, int64_t count, int64_t blk) {
