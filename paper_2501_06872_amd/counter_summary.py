@@ -39,8 +39,8 @@ PASSES = {
             "SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_LEVEL_WAVES", "SQ_CYCLES",
             "TCC_ATOMIC", "TCC_EA0_WRREQ", "TCC_EA0_WRREQ_64B", "TCC_EA0_RDREQ"],
 }
-KERNELS = ("k_hist", "k_lsd_pass0", "k_lsd_pass1", "k_lsd_pass2", "k_big_count", "k_big_scan", "k_final",
-           "k_hlh_count", "k_hlh_scatter")
+KERNELS = ("k_hist", "k_lsd_pass0", "k_tile_hist", "k_lsd_pass1", "k_lsd_pass2", "k_big_count", "k_big_scan",
+           "k_final", "k_hlh_count", "k_hlh_scatter")
 
 
 def command(workload, tag):
