@@ -50,6 +50,8 @@ def kernel_bytes(name, n, m, w, passes, packed=False):
     6 + w bytes per edge (16-bit key, source word) instead of 8 + w."""
     if name == "k_hist":
         return 4 * m
+    if name == "k_tile_hist":  # read a later pass's input keys (2-byte packed keys in a two-pass plan)
+        return (2 if packed else 4) * m
     if name.startswith("k_lsd_pass"):
         p = int(name[-1])
         first, last = p == 0, p == passes - 1

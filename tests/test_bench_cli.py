@@ -36,6 +36,9 @@ def test_byte_model_of_the_dominant_kernels():
     assert bench.kernel_bytes("k_lsd_pass0", n, m, 0, 2, packed=True) == 4 * m + 8 * (n + 1) + 6 * m
     assert bench.kernel_bytes("k_lsd_pass1", n, m, 4, 2, packed=True) == 10 * m + 10 * m
     assert bench.kernel_bytes("k_final", n, m, 0, 2) == 6 * m + 4 * m + 8 * (n + 1)
+    # a later pass's tile counts: one read of its input keys
+    assert bench.kernel_bytes("k_tile_hist", n, m, 0, 2, packed=True) == 2 * m
+    assert bench.kernel_bytes("k_tile_hist", n, m, 4, 3) == 4 * m
     assert bench.path_alg_bytes(n, m, 0) == 2 * (8 * (n + 1) + 4 * m) + 8 * n
 
 
