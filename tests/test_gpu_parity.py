@@ -416,10 +416,12 @@ def test_csc_input_transposes_back_to_the_csr(hip_device, permute, payload):
 
 @pytest.mark.parametrize("variant", [1, 3, 4])
 def test_first_pass_tile_counts(hip_device, variant):
-    """The first partition pass places each tile with the column prefix of
-    k_hist's per-tile digit counts (16-bit per tile and digit): a tile whose
-    edges all share one digit (the largest count a tile can hold), edge
-    counts around whole tiles and a ragged last tile, one and two passes."""
+    """Every partition pass places each tile with the column prefix of
+    per-tile digit counts (16-bit per tile and digit; k_hist's for the first
+    pass, k_tile_hist's over the previous pass's keys for a later one): a
+    tile whose edges all share one digit (the largest count a tile can
+    hold), edge counts around whole tiles and a ragged last tile, one pass,
+    two passes (packed 16-bit keys between them) and three (32-bit keys)."""
     tile = {1: 8192, 3: 4096, 4: 16384}[variant]
     rng = np.random.default_rng(variant)
     for m in (1, 3, tile - 1, tile, tile + 1, 3 * tile + 5):
@@ -431,6 +433,7 @@ def test_first_pass_tile_counts(hip_device, variant):
             D[::7] = rng.integers(0, n, size=D[::7].size)
         for u in range(n):
             D[O[u]:O[u + 1]].sort()
-        for fb, db in ((9, 9), (4, 5)):
-            assert_parity(O, D, None, hip_device, f"tile counts variant {variant} m={m} fine={fb} digit={db}",
-                          policy=1, fine_bits=fb, digit_bits=db, variant=variant)
+        for fb, db, passes in ((9, 9, 1), (4, 5, 2), (2, 4, 3)):
+            params = assert_parity(O, D, None, hip_device, f"tile counts variant {variant} m={m} fine={fb} digit={db}",
+                                   policy=1, fine_bits=fb, digit_bits=db, variant=variant)
+            assert params["passes"] == passes, params
