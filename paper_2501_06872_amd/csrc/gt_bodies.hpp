@@ -467,7 +467,9 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   // places them with the offsets of k_tile_hist's counts or takes them from
   // a ticket and runs a decoupled look-back over them.
   const int64_t ntiles = (a.m + TILE - 1) / TILE;
-  const int64_t order = s_tile;  // position in the look-back chain
+  // position in the look-back chain; below 2^31 (a tile holds at least 4096
+  // edges), read into a scalar register so the tile's bounds are scalar too
+  const int64_t order = (int64_t)__builtin_amdgcn_readfirstlane((int)s_tile);
   const int64_t tile = CSR_IN ? ntiles - 1 - order : order;
   const int64_t base = tile * TILE;
   const int64_t cnt64 = a.m - base < TILE ? a.m - base : TILE;
@@ -515,7 +517,7 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   }
   // first pass: the source of the tile's first edge and the first offset
   // each thread inspects for the source marks (loaded after the staging)
-  int64_t u0 = 0, o_first = 0;
+  int64_t u0 = 0, u_end = 0, o_first = 0;
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
   // Local positions stay below the tile size: two per register.
@@ -595,6 +597,9 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   if constexpr (!kEarly) load_src_pay();
   if constexpr (CSR_IN) {  // loaded here, where fewer values are live
     u0 = a.tile_src0[tile];
+    // the last source that can start inside the tile: the next tile's first
+    // edge's source (every later source starts after the tile)
+    u_end = tile + 1 < ntiles ? (int64_t)a.tile_src0[tile + 1] : a.n - 1;
     const int64_t u = u0 + 1 + tid;
     o_first = u < a.n ? a.O[u] : a.m;
   }
@@ -699,11 +704,10 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
       __syncthreads();
       if (tid == 0) s_stage[0] = (uint32_t)u0;
       int64_t o = o_first;
-      for (int64_t u = u0 + 1 + tid; u < a.n;) {
-        if (o >= base + cnt64) break;
-        if (o > base) atomicMax(&s_stage[o - base], (uint32_t)u);
+      for (int64_t u = u0 + 1 + tid; u <= u_end;) {
+        if (o > base && o < base + cnt64) atomicMax(&s_stage[o - base], (uint32_t)u);
         u += NT;
-        if (u < a.n) o = a.O[u];
+        if (u <= u_end) o = a.O[u];
       }
       __syncthreads();
       // running maximum along the wave's rows, kept in registers (each
