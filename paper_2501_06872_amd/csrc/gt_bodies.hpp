@@ -517,7 +517,7 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   }
   // first pass: the source of the tile's first edge and the first offset
   // each thread inspects for the source marks (loaded after the staging)
-  int64_t u0 = 0, u_end = 0, o_first = 0;
+  int64_t u0 = 0, o_first = 0;
 
   // In-wave stable ranking: rows in edge order, peers matched through LDS.
   // Local positions stay below the tile size: two per register.
@@ -597,9 +597,6 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
   if constexpr (!kEarly) load_src_pay();
   if constexpr (CSR_IN) {  // loaded here, where fewer values are live
     u0 = a.tile_src0[tile];
-    // the last source that can start inside the tile: the next tile's first
-    // edge's source (every later source starts after the tile)
-    u_end = tile + 1 < ntiles ? (int64_t)a.tile_src0[tile + 1] : a.n - 1;
     const int64_t u = u0 + 1 + tid;
     o_first = u < a.n ? a.O[u] : a.m;
   }
@@ -703,11 +700,24 @@ __device__ __forceinline__ void lsd_body(const LsdArgs &a, int64_t order_in,
       lds_zero16(s_stage, TILE * 4, tid, NT);
       __syncthreads();
       if (tid == 0) s_stage[0] = (uint32_t)u0;
+      // the last source that can start inside the tile: the next tile's
+      // first edge's source (every later source starts after the tile).
+      // Vertex IDs are below 2^31, so the walk stays in 32 bits.
       int64_t o = o_first;
-      for (int64_t u = u0 + 1 + tid; u <= u_end;) {
-        if (o > base && o < base + cnt64) atomicMax(&s_stage[o - base], (uint32_t)u);
-        u += NT;
-        if (u <= u_end) o = a.O[u];
+      if constexpr (PK_OUT) {
+        const uint32_t u_end = tile + 1 < ntiles ? (uint32_t)a.tile_src0[tile + 1] : (uint32_t)(a.n - 1);
+        for (uint32_t u = (uint32_t)u0 + 1u + (uint32_t)tid; u <= u_end;) {
+          if (o > base && o < base + cnt64) atomicMax(&s_stage[o - base], u);
+          u += NT;
+          if (u <= u_end) o = a.O[u];
+        }
+      } else {
+        for (int64_t u = u0 + 1 + tid; u < a.n;) {
+          if (o >= base + cnt64) break;
+          if (o > base) atomicMax(&s_stage[o - base], (uint32_t)u);
+          u += NT;
+          if (u < a.n) o = a.O[u];
+        }
       }
       __syncthreads();
       // running maximum along the wave's rows, kept in registers (each
